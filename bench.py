@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the FP64 CTU-PPM + HLLC hydro step on one MI355X.
+
+A step is the whole hot path on one box: ghost fill + CFL timestep reduction
+(estimate_dt) and the advance (advance_box), all on the device, inputs
+resident in HBM before timing starts.  The headline workload is the 512^3
+Rayleigh-Taylor box (FP64, gamma = 1.4, g = -0.1 z, reflecting z walls);
+`value` = valid cells x timed steps / device time (HIP events on the stream
+the library launches on), in cell-updates per second.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel group's achieved FP64 rate (algorithmic
+                flops per cell-update, counted by the oracle's operation-
+                counting build, x cells / that group's average device time per
+                step, from HIP events recorded by the library around it)
+                against the FP64 VALU issue peak of the chip
+  cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
+                same workload (rank 0, N = 1 only)
+  also          secondary workloads: the 256^3 Kelvin-Helmholtz box, and the
+                512-box batched level (one launch per stage for all boxes)
+                against the same boxes launched one by one
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads ...]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 VALU issue peak without FMA: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz
+# (each add or multiply is one instruction; the 78.6 TFLOP/s vector figure
+# counts an FMA as two flops)
+PEAK_FP64_NOFMA = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workloads", default="rt512,kh256,level",
+                    help="comma list of rt512, kh256, level")
+    ap.add_argument("--level-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def time_box(hydro, torch, U, box, prm, steps, warmup):
+    B = hydro.Box(U, box, prm)
+    for _ in range(warmup):
+        B.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        B.step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # per-stage device time, in a separate pass with the library's stage events
+    timer = hydro.StageTimer()
+    for _ in range(steps):
+        with timer:
+            B.step()
+    err = int(B.err.item())
+    del B
+    torch.cuda.empty_cache()
+    return ms, wall, timer, err
+
+
+def time_level(hydro, torch, inputs, steps, warmup):
+    states, boxes, prm = inputs.level(nboxes=512, seed=2)
+    cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in boxes)
+    lev = hydro.Level(states, boxes, prm, shared_dt=True)
+    for _ in range(warmup):
+        lev.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        lev.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1)
+    del lev
+    torch.cuda.empty_cache()
+    # the same boxes, one library call per box and stage (one stream)
+    Us = [torch.tensor(u, device="cuda") for u in states]
+    Uns = [torch.empty_like(u) for u in Us]
+    ws = hydro.alloc_workspace(max(boxes, key=lambda b: hydro.workspace_bytes(b)))
+    dts = torch.zeros(len(boxes), dtype=torch.float64, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def per_box_step():
+        for b in range(len(boxes)):
+            hydro.estimate_dt(Us[b], boxes[b], prm, dts[b:b + 1])
+        dmin = dts.min().reshape(1)
+        for b in range(len(boxes)):
+            hydro.advance_box(Us[b], Uns[b], boxes[b], prm, dmin, ws, err)
+        for b in range(len(boxes)):
+            Us[b], Uns[b] = Uns[b], Us[b]
+
+    for _ in range(warmup):
+        per_box_step()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        per_box_step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_per_box = e0.elapsed_time(e1)
+    del Us, Uns, ws
+    torch.cuda.empty_cache()
+    return {"workload": "level512", "boxes": len(boxes), "cells": cells, "steps": steps,
+            "batched_cu_per_s": cells * steps / (ms_batched * 1e-3),
+            "per_box_cu_per_s": cells * steps / (ms_per_box * 1e-3),
+            "batched_ms_per_step": ms_batched / steps, "per_box_ms_per_step": ms_per_box / steps}
+
+
+def cpu_baseline(inputs, U, box, prm, seconds):
+    """The oracle on z-slabs of the workload's first step until ~`seconds`
+    of host time have been spent."""
+    from oracle import build, oracle as orc
+    build.build(force=False)
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    U = U.copy()
+    orc.fill_ghosts(U, ob)
+    dt = orc.estimate_dt(U, ob, op)
+    ops = orc.opcount_cell(U, ob, op, dt, N=10)
+    n = box["n"]
+    Unew = U.copy()
+    slab = 4
+    cells = 0
+    t0 = time.perf_counter()
+    z = 0
+    while time.perf_counter() - t0 < seconds and z < n[2]:
+        hi = min(n[2], z + slab)
+        orc.advance_region(U, Unew, ob, op, dt, (0, 0, z), (n[0], n[1], hi))
+        cells += n[0] * n[1] * (hi - z)
+        z = hi
+    el = time.perf_counter() - t0
+    return ({"value": cells / el, "unit": "cell-updates/s", "cores": orc.num_threads(),
+             "kind": "oracle",
+             "sample": "first step of the %dx%dx%d workload on %d z-slabs of %d cells "
+                       "(%d cell-updates, %.1f s)" % (n[0], n[1], n[2], z // slab, slab,
+                                                      cells, el)}, ops)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2007_05218_amd import hydro, inputs
+    hydro.lib()
+    work = [w.strip() for w in args.workloads.split(",") if w.strip()]
+    rank = int(os.environ.get("RANK", "0"))
+
+    log("building RT 512^3 input")
+    U, box, prm = inputs.rt(512, seed=4)
+    ncell = box["n"][0] * box["n"][1] * box["n"][2]
+    log("timing RT 512^3: %d warmup + %d steps" % (args.warmup, args.steps))
+    ms, wall, timer, err = time_box(hydro, torch, U, box, prm, args.steps, args.warmup)
+    value = ncell * args.steps / (ms * 1e-3)
+    log("RT512: %.3f ms/step, %.3e cu/s, err=%d" % (ms / args.steps, value, err))
+    stage_ms = {k: v / max(timer.calls, 1) for k, v in timer.total_ms.items()}
+    log("stage ms/step:", json.dumps({k: round(v, 3) for k, v in stage_ms.items()}))
+
+    cpu = None
+    ops = None
+    if rank == 0 and not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu, ops = cpu_baseline(inputs, U, box, prm, args.cpu_seconds)
+        log("cpu baseline:", json.dumps(cpu), "ops/cell:", json.dumps(ops))
+    flops_cell = (ops["add"] + ops["mul"] + ops["div"] + ops["sqrt"]) if ops else None
+
+    # dominant kernel group and its roofline
+    dom = max((k for k in stage_ms if k not in ("fill", "dt")), key=lambda k: stage_ms[k])
+    adv_ms = sum(v for k, v in stage_ms.items() if k not in ("fill", "dt"))
+    roof = None
+    if flops_cell:
+        # the whole advance's algorithmic flops credited to the advance's time;
+        # the dominant group's share is reported beside it
+        ach = flops_cell * ncell / (adv_ms * 1e-3)
+        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_NOFMA / 1e12,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_NOFMA, "traffic": None,
+                "kernel": "advance (all stages)", "dominant_stage": dom,
+                "dominant_stage_ms": stage_ms[dom], "advance_ms": adv_ms,
+                "flops_per_cell_update": flops_cell,
+                "hbm_frac_on_80B_per_cu": 80.0 * ncell / (adv_ms * 1e-3) / HBM_PEAK}
+
+    also = {}
+    if "kh256" in work:
+        U2, box2, prm2 = inputs.kh(256, seed=1)
+        n2 = 256 ** 3
+        log("timing KH 256^3")
+        ms2, _, t2, e2 = time_box(hydro, torch, U2, box2, prm2, args.steps, args.warmup)
+        also["kh256"] = {"cu_per_s": n2 * args.steps / (ms2 * 1e-3),
+                         "ms_per_step": ms2 / args.steps, "err": e2}
+        del U2
+    if "level" in work:
+        log("timing the 512-box level, batched vs per-box")
+        also["level512"] = time_level(hydro, torch, inputs, args.level_steps, 1)
+
+    out = {"metric": "FP64 hydro cell-updates/s (whole step: ghost fill + CFL dt + CTU-PPM-HLLC advance)",
+           "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "rt512: Rayleigh-Taylor 512^3 box, FP64 SoA, 4 ghosts, "
+                                  "gamma 1.4, g=-0.1 z, CFL 0.5, seed 4",
+                      "cells": ncell, "parallelism": "single GPU"},
+           "stage_ms_per_step": stage_ms, "err_bits": err,
+           "roofline": roof, "cpu_baseline": cpu, "also": also}
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

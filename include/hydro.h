@@ -1,0 +1,169 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) FP64 hydrodynamics library.
+ *
+ * One time step of the unsplit corner-transport-upwind (CTU) PPM scheme with
+ * an HLLC Riemann solver for a gamma-law gas, on boxes of cells with ghost
+ * layers.  The paper (Katz et al. 2020) describes this hydro only in outline
+ * -- a slope stencil over neighbouring zones reconstructing a polynomial
+ * (Sec. III), boxes of multi-component fluid data distributed as a list
+ * (Sec. II, Fig. 1), small boxes batched over streams (Sec. IV-A), a timestep
+ * proportional to the zone width (Sec. V) -- and takes the scheme from its
+ * Castro reference (bibliography entry CastroI).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers; box/params descriptors are
+ *    host pointers unless named *_dev.  The caller owns every buffer; the
+ *    library never allocates or frees device memory in these calls (plans
+ *    own one device buffer, allocated in hydro_plan_create).
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream) and is asynchronous: no call synchronises the host.
+ *  - Argument errors are reported synchronously (HYDRO_EINVAL, nothing is
+ *    enqueued); launch failures return HYDRO_EHIP.  Numerical problems are
+ *    OR-ed into the caller's device int32 *err_dev (HYDRO_ERR_* bits), which
+ *    the caller reads after synchronising.  No call throws or aborts.
+ *  - The timestep is passed by device pointer so a whole step can be
+ *    captured in a HIP graph.
+ *  - Calls on different streams with disjoint buffers do not interact.
+ *
+ * State layout (a "Fab", Sec. II): a box has n[3] valid cells and ng ghost
+ * layers per side.  One component is a dense array of s0*s1*s2 doubles,
+ * s_d = n_d + 2 ng, x fastest; the five components rho, rho*u, rho*v, rho*w,
+ * E (total energy density) follow one another (structure of arrays).  Cell
+ * (i,j,k), -ng <= i < n0+ng, lives at ((k+ng)*s1 + (j+ng))*s0 + (i+ng).
+ * hydro_state_elems() gives the total number of doubles (5 s0 s1 s2).
+ *
+ * Arithmetic: IEEE binary64 throughout, no fused multiply-add contraction,
+ * correctly rounded division and square root; results do not depend on the
+ * launch configuration, on the batch a box is advanced in, or on the
+ * stream.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HYDRO_OK = 0,
+    HYDRO_EINVAL = 1, /* invalid argument; nothing enqueued            */
+    HYDRO_EHIP = 2,   /* a HIP runtime call or kernel launch failed     */
+    HYDRO_ENOWS = 3   /* the workspace passed is smaller than required  */
+} hydro_status;
+
+typedef enum {
+    HYDRO_BC_PERIODIC = 0, /* ghost = valid cell one period away               */
+    HYDRO_BC_OUTFLOW = 1,  /* ghost = nearest valid cell (zero gradient)       */
+    HYDRO_BC_REFLECT = 2   /* ghost = mirror image, normal momentum negated     */
+} hydro_bc;
+
+/* error bits OR-ed into *err_dev */
+enum {
+    HYDRO_ERR_NONFINITE = 1, /* an updated value is NaN or Inf                       */
+    HYDRO_ERR_RHO = 2,       /* an updated density is <= 0                           */
+    HYDRO_ERR_P = 4,         /* an updated pressure is <= 0                          */
+    HYDRO_ERR_FALLBACK = 8   /* a transverse-corrected face state had rho<=0 or p<=0 and
+                                the uncorrected state was used (informational)       */
+};
+
+/* A box (Sec. II "Box"/"Fab"): 64 bytes, 8-byte aligned. */
+typedef struct hydro_box {
+    int32_t n[3];     /* valid cells per axis, >= 1; >= ng on periodic/reflect axes */
+    int32_t ng;       /* ghost layers per side, 3 <= ng <= 8 (the stencil reads 3)  */
+    double dx[3];     /* cell widths, > 0                                           */
+    int32_t bc_lo[3]; /* hydro_bc at the low face of each axis                      */
+    int32_t bc_hi[3]; /* hydro_bc at the high face; periodic must be paired         */
+} hydro_box;
+
+/* Physical and numerical parameters. */
+typedef struct hydro_params {
+    double gamma;   /* ratio of specific heats, > 1                    */
+    double cfl;     /* Courant number, 0 < cfl <= 1                    */
+    double grav[3]; /* constant gravitational acceleration (lab axes)  */
+} hydro_params;
+
+/* Doubles in one state array of `box` (all five components, with ghosts);
+ * 0 for an invalid box. */
+size_t hydro_state_elems(const hydro_box *box);
+
+/* Device workspace, in bytes, that advance_box (nboxes = 1) or advance_boxes
+ * needs for these boxes; 0 for invalid boxes. */
+size_t hydro_workspace_bytes(const hydro_box *boxes, int nboxes);
+
+/* Ghost fill (the neighbour data of Sec. II/IV-A): every ghost cell of U_dev
+ * takes the value of the valid cell it maps to under the box's boundary
+ * kinds, mapped axis by axis, so edges and corners are defined; reflected
+ * axes negate their momentum component.  In place. */
+hydro_status hydro_fill_ghosts(double *U_dev, const hydro_box *box, void *stream);
+
+/* CFL timestep (Sec. V: dt proportional to the zone width): fills the
+ * ghosts of U_dev (as hydro_fill_ghosts), then writes to *dt_dev
+ *     dt = cfl * min over axes d of dx_d / max over valid cells (|u_d| + c),
+ * c = sqrt(gamma p / rho).  The result is exact (min/max are exact) and
+ * independent of the launch.  *dt_dev is used as the reduction's accumulator;
+ * no other scratch is needed. */
+hydro_status estimate_dt(double *U_dev, const hydro_box *box, const hydro_params *prm,
+                         double *dt_dev, void *stream);
+
+/* One CTU-PPM-HLLC step of length *dt_dev (Sec. III's reconstruction
+ * stencil; the scheme of the paper's CastroI reference): writes the valid
+ * cells of U_new_dev from U_dev, whose ghosts must be filled (estimate_dt
+ * does it).  Ghost cells of U_new_dev are not written.  U_new_dev must not
+ * overlap U_dev.  ws_dev must hold hydro_workspace_bytes(box, 1) bytes
+ * (HYDRO_ENOWS otherwise), aligned to 256 bytes; its contents on entry do
+ * not matter.  Error bits go to *err_dev (not cleared by the call). */
+hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box *box,
+                         const hydro_params *prm, const double *dt_dev, void *ws_dev,
+                         size_t ws_bytes, int32_t *err_dev, void *stream);
+
+/* Batched timestep over a list of boxes (a level of Sec. II's MultiFab):
+ * fills the ghosts of every box, writes each box's dt to dt_dev[b] and, if
+ * dt_min_dev is not NULL, the minimum over boxes to *dt_min_dev.
+ * U_ptrs_dev[b] (device array of nb device pointers) is box b's state;
+ * `boxes` is the host array of nb boxes given to hydro_plan_create for
+ * `plan`.  Each dt_dev[b] is bitwise the value estimate_dt gives for box b. */
+hydro_status estimate_dt_boxes(int nb, double *const *U_ptrs_dev, const void *plan,
+                               const hydro_params *prm, double *dt_dev,
+                               double *dt_min_dev, void *stream);
+
+/* Batched step (Sec. IV-A: many boxes per GPU instead of one stream per
+ * box): advances every box of `plan` by its own timestep dt_dev[b]
+ * (dt_stride = 1) or by one shared timestep dt_dev[0] (dt_stride = 0), with
+ * one launch per stage for all boxes together.  Every box's result is
+ * bitwise the one advance_box gives it.  ws_dev must hold
+ * hydro_workspace_bytes(boxes, nb) bytes. */
+hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
+                           double *const *U_new_ptrs_dev, const void *plan,
+                           const hydro_params *prm, const double *dt_dev, int dt_stride,
+                           void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream);
+
+/* Plan for a fixed list of boxes: validates them, chooses the tile shapes
+ * (autotune_json: NULL for the built-in table, else a JSON object mapping
+ * shape classes to tiles as written by the package's autotuner) and builds
+ * the device work list.  *plan receives an opaque handle. */
+hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,
+                               void **plan);
+void hydro_plan_destroy(void *plan);
+
+/* Profiling aid.  The library's kernels form hydro_stage_count() stage
+ * groups (hydro_stage_name(s): "fill", "dt", ... in launch order).  After
+ * hydro_set_stage_events(ev) with ev an array of 2*hydro_stage_count() HIP
+ * events (hipEvent_t, created by the caller), every call records ev[2s] on
+ * its stream before the first launch of stage group s and ev[2s+1] after the
+ * last, so the caller can read each group's device time with
+ * hipEventElapsedTime after synchronising.  NULL switches recording off.
+ * Process-wide setting; not meant for concurrent calls. */
+int hydro_stage_count(void);
+const char *hydro_stage_name(int s);
+hydro_status hydro_set_stage_events(void *const *events);
+
+/* Human-readable name of a status code (static string). */
+const char *hydro_status_string(hydro_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYDRO_H */

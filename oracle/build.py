@@ -12,19 +12,30 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hydro_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+OPC_SRC = os.path.join(HERE, "opcount.cpp")
+OPC_LIB = os.path.join(HERE, "libopcount.so")
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c11",
           "-shared", "-fPIC", "-Wall"]
 
 
+def _stale(lib, srcs):
+    return not os.path.exists(lib) or os.path.getmtime(lib) < max(os.path.getmtime(s) for s in srcs)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle; returns the path of the shared library."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    """Compile the oracle (and its operation-counting variant); returns the
+    path of the oracle library."""
+    hdr = os.path.join(HERE, "hydro_oracle.h")
+    if force or _stale(LIB, [SRC, hdr]):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"], check=True)
+        os.replace(tmp, LIB)
+    if force or _stale(OPC_LIB, [SRC, hdr, OPC_SRC]):
+        tmp = OPC_LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["g++", "-O1", "-ffp-contract=off", "-std=c++17", "-fPIC", "-shared",
+                        "-w", "-o", tmp, OPC_SRC], check=True)
+        os.replace(tmp, OPC_LIB)
     return LIB
 
 

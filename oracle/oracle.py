@@ -192,3 +192,21 @@ def cons_of_prim(q, gamma):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def opcount_cell(U, box, prm, dt, N=8):
+    """Operations of one cell-update (add, mul, div, sqrt, cmp) counted by the
+    operation-counting build of the oracle on the data of U (ghosts filled)."""
+    path = _build.OPC_LIB
+    if not os.path.exists(path):
+        _build.build()
+    L = C.CDLL(path)
+    L.orc_opcount_cell.argtypes = [C.POINTER(C.c_double), C.POINTER(OrcBox),
+                                   C.POINTER(OrcParams), C.c_double, C.c_int,
+                                   C.POINTER(C.c_double)]
+    ops = np.zeros(5)
+    rc = L.orc_opcount_cell(_dp(np.ascontiguousarray(U)), C.byref(box), C.byref(prm), dt, N,
+                            _dp(ops))
+    if rc != 0:
+        raise RuntimeError("orc_opcount_cell failed")
+    return dict(zip(("add", "mul", "div", "sqrt", "cmp"), ops.tolist()))

@@ -1,0 +1,937 @@
+// hydro.hip -- gfx950 kernels and the C ABI (include/hydro.h) of one
+// CTU-PPM-HLLC hydro step on boxes with ghost cells.
+//
+// Stage pipeline (one launch per stage and direction, covering one box or a
+// whole batch of boxes; intermediates live in the caller's HBM workspace,
+// one dense ghosted array per field, x fastest, so every access is a
+// coalesced unit-stride stream along x):
+//   fill    ghost cells of U from the boundary kinds (one pass: each axis
+//           maps independently, so edges and corners need no ordering)
+//   dt      per-cell min_d dx_d/(|u_d|+c), wave64 shuffle -> LDS -> one
+//           64-bit atomicMin per block on the bit pattern (positive doubles
+//           order like unsigned integers), scaled by cfl
+//   prim    rho,u,v,w,p,c on every cell of the ghosted box
+//   trace   PPM + characteristic tracing, both faces, each direction, on the
+//           cells one beyond the valid region, + half-step gravity kick
+//   flux1   HLLC on the traced states at every face the corner step reads
+//   flux2   corner coupling (dt/3 transverse corrections) + HLLC: six
+//           (normal | transverse) flux families
+//   flux3   final states (dt/2 corrections by both round-2 transverse flux
+//           differences) + HLLC
+//   update  conservative update + time-centred gravity source + error bits
+//
+// Batching: a plan lists, for every stage, the prefix sum of each box's
+// block count; a block finds its box by binary search, so one launch per
+// stage serves hundreds of uneven boxes (the per-box launches of the
+// paper's Sec. IV-A replaced by one launch over the whole list).
+#include "hydro_common.h"
+#include "../../include/hydro.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+using namespace hydro;
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct Geo {
+    int n[3];
+    int ng;
+    int s[3];
+    long long cs;  // doubles per component (s0*s1*s2)
+    double dx[3];
+    int bc_lo[3], bc_hi[3];
+};
+
+// workspace fields
+constexpr int P_R = 0, P_U = 1, P_V = 2, P_W = 3, P_P = 4, P_C = 5;
+__host__ __device__ constexpr int QHI(int d, int v) { return 6 + d * 10 + v; }
+__host__ __device__ constexpr int QLO(int d, int v) { return 6 + d * 10 + 5 + v; }
+__host__ __device__ constexpr int F1F(int d, int v) { return 36 + d * 5 + v; }
+__host__ __device__ constexpr int FAM(int t, int s) { return t * 2 + (s < t ? s : s - 1); }
+__host__ __device__ constexpr int F2F(int fam, int v) { return 51 + fam * 5 + v; }
+__host__ __device__ constexpr int F3F(int d, int v) { return 81 + d * 5 + v; }
+constexpr int kFields = 96;
+
+// stages (block-count prefix arrays are kept per stage)
+enum {
+    ST_FILL = 0, ST_DT = 1, ST_PRIM = 2, ST_TRACE = 3, ST_F1 = 4, ST_F2 = 7, ST_F3 = 13,
+    ST_UPD = 16, ST_COUNT = 17
+};
+constexpr int kDtCellsPerThread = 4;
+constexpr long long kDtMaxBlocks = 4096;
+
+__host__ __device__ __forceinline__ long long field_doubles(long long cs)
+{
+    return (cs + 31) / 32 * 32;
+}
+
+__device__ __forceinline__ long long cell(const Geo &g, int i, int j, int k)
+{
+    return ((long long)(k + g.ng) * g.s[1] + (j + g.ng)) * g.s[0] + (i + g.ng);
+}
+
+__device__ __forceinline__ long long stride(const Geo &g, int d)
+{
+    return d == 0 ? 1LL : (d == 1 ? (long long)g.s[0] : (long long)g.s[0] * g.s[1]);
+}
+
+struct WS {
+    double *base;
+    long long fs;  // doubles per field
+    __device__ __forceinline__ double *f(int idx) const { return base + idx * fs; }
+};
+
+struct Reg {
+    int lo[3];
+    int ext[3];
+};
+
+// index region of a stage (cells; a face f along d is stored at cell f)
+__host__ __device__ inline Reg stage_reg(const Geo &g, int st)
+{
+    Reg r;
+    const int *n = g.n;
+    int lo[3] = {0, 0, 0}, hi[3] = {n[0], n[1], n[2]};
+    if (st == ST_PRIM) {
+        for (int e = 0; e < 3; ++e) { lo[e] = -g.ng; hi[e] = n[e] + g.ng; }
+    } else if (st == ST_TRACE) {
+        for (int e = 0; e < 3; ++e) { lo[e] = -1; hi[e] = n[e] + 1; }
+    } else if (st >= ST_F1 && st < ST_F1 + 3) {
+        int d = st - ST_F1;
+        for (int e = 0; e < 3; ++e) { lo[e] = -1; hi[e] = n[e] + 1; }
+        lo[d] = 0;
+    } else if (st >= ST_F2 && st < ST_F2 + 6) {
+        int fam = st - ST_F2;
+        int t = fam / 2, r2 = fam % 2;
+        int sd = r2 < t ? r2 : r2 + 1;
+        int d = 3 - t - sd;
+        lo[t] = 0; hi[t] = n[t] + 1;
+        lo[sd] = 0; hi[sd] = n[sd];
+        lo[d] = -1; hi[d] = n[d] + 1;
+    } else if (st >= ST_F3 && st < ST_F3 + 3) {
+        hi[st - ST_F3] = n[st - ST_F3] + 1;
+    }
+    for (int e = 0; e < 3; ++e) {
+        r.lo[e] = lo[e];
+        r.ext[e] = hi[e] - lo[e];
+    }
+    return r;
+}
+
+__host__ __device__ inline long long reg_count(const Reg &r)
+{
+    return (long long)r.ext[0] * r.ext[1] * r.ext[2];
+}
+
+__device__ __forceinline__ bool reg_cell(const Reg &r, long long t, int &i, int &j, int &k)
+{
+    if (t < 0 || t >= reg_count(r)) return false;
+    i = r.lo[0] + (int)(t % r.ext[0]);
+    t /= r.ext[0];
+    j = r.lo[1] + (int)(t % r.ext[1]);
+    k = r.lo[2] + (int)(t / r.ext[1]);
+    return true;
+}
+
+// work items of a stage for one box
+__host__ inline long long stage_items(const Geo &g, int st)
+{
+    long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
+    if (st == ST_FILL) return g.cs - nv;
+    if (st == ST_DT) return nv;
+    return reg_count(stage_reg(g, st));
+}
+
+__host__ inline long long stage_blocks(const Geo &g, int st)
+{
+    long long items = stage_items(g, st);
+    if (st == ST_DT) {
+        long long b = (items + (long long)kBlock * kDtCellsPerThread - 1) /
+                      ((long long)kBlock * kDtCellsPerThread);
+        return b < 1 ? 1 : (b > kDtMaxBlocks ? kDtMaxBlocks : b);
+    }
+    return (items + kBlock - 1) / kBlock;
+}
+
+// ---------------------------------------------------------------- launch args
+
+// One launch covers either a single box (nb == 0; everything by value) or a
+// batch (nb >= 1; per-box data in device arrays of a plan).
+struct Launch {
+    // single box
+    Geo g;
+    const double *U;
+    double *Un;
+    double *ws;
+    const double *dt;
+    // batch
+    int nb;
+    const Geo *geos;
+    const unsigned *pre;  // this stage's block prefix, nb+1 entries
+    const double *const *Us;
+    double *const *Uns;
+    const long long *wsoff;  // doubles from the workspace base
+    const double *dts;
+    int dt_stride;
+};
+
+struct Box1 {
+    Geo g;
+    const double *U;
+    double *Un;
+    WS ws;
+    const double *dt;
+    int b;            // box index within the batch (0 for a single box)
+    long long blk;    // block index within the box
+    long long nblk;   // blocks of this box in this stage
+};
+
+__device__ __forceinline__ Box1 resolve(const Launch &L)
+{
+    Box1 o;
+    if (L.nb == 0) {
+        o.g = L.g;
+        o.U = L.U;
+        o.Un = L.Un;
+        o.ws.base = L.ws;
+        o.dt = L.dt;
+        o.b = 0;
+        o.blk = blockIdx.x;
+        o.nblk = gridDim.x;
+    } else {
+        // largest b with pre[b] <= blockIdx.x
+        int lo = 0, hi = L.nb;
+        const unsigned x = blockIdx.x;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (L.pre[mid] <= x) lo = mid;
+            else hi = mid;
+        }
+        o.b = lo;
+        o.g = L.geos[lo];
+        o.U = L.Us ? L.Us[lo] : nullptr;
+        o.Un = L.Uns ? L.Uns[lo] : nullptr;
+        o.ws.base = L.ws ? L.ws + L.wsoff[lo] : nullptr;
+        o.dt = L.dts ? L.dts + (long long)lo * L.dt_stride : nullptr;
+        o.blk = x - L.pre[lo];
+        o.nblk = L.pre[lo + 1] - L.pre[lo];
+    }
+    o.ws.fs = field_doubles(o.g.cs);
+    return o;
+}
+
+// ---------------------------------------------------------------- ghost fill
+
+__device__ __forceinline__ int ghost_src(int g, int n, int bl, int bh, int &flip)
+{
+    if (g < 0) {
+        int m = -1 - g;
+        if (bl == HYDRO_BC_PERIODIC) return n - 1 - m;
+        if (bl == HYDRO_BC_OUTFLOW) return 0;
+        flip = 1;
+        return m;
+    }
+    if (g >= n) {
+        int m = g - n;
+        if (bh == HYDRO_BC_PERIODIC) return m;
+        if (bh == HYDRO_BC_OUTFLOW) return n - 1;
+        flip = 1;
+        return n - 1 - m;
+    }
+    return g;
+}
+
+// dt_bits (per box, may be null) and dtmin_bits (may be null) are reset to
+// +inf here so the following dt launch can min-reduce into them
+__global__ void __launch_bounds__(kBlock) k_fill(Launch L, unsigned long long *dt_bits,
+                                                 unsigned long long *dtmin_bits)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    double *U = const_cast<double *>(o.U);
+    long long t = o.blk * kBlock + threadIdx.x;
+    if (t == 0) {
+        if (dt_bits) dt_bits[o.b] = 0x7FF0000000000000ULL;
+        if (dtmin_bits && o.b == 0) *dtmin_bits = 0x7FF0000000000000ULL;
+    }
+    const long long s0 = g.s[0], s1 = g.s[1];
+    const long long ng2 = 2LL * g.ng;
+    const long long cz = ng2 * s1 * s0;
+    const long long cy = (long long)g.n[2] * ng2 * s0;
+    const long long cx = (long long)g.n[2] * g.n[1] * ng2;
+    if (t >= cz + cy + cx) return;
+    int i, j, k;
+    if (t < cz) {
+        i = (int)(t % s0) - g.ng;
+        t /= s0;
+        j = (int)(t % s1) - g.ng;
+        int kk = (int)(t / s1);
+        k = kk < g.ng ? kk - g.ng : g.n[2] + (kk - g.ng);
+    } else if (t < cz + cy) {
+        t -= cz;
+        i = (int)(t % s0) - g.ng;
+        t /= s0;
+        int jj = (int)(t % ng2);
+        j = jj < g.ng ? jj - g.ng : g.n[1] + (jj - g.ng);
+        k = (int)(t / ng2);
+    } else {
+        t -= cz + cy;
+        int ii = (int)(t % ng2);
+        i = ii < g.ng ? ii - g.ng : g.n[0] + (ii - g.ng);
+        t /= ng2;
+        j = (int)(t % g.n[1]);
+        k = (int)(t / g.n[1]);
+    }
+    int fx = 0, fy = 0, fz = 0;
+    int si = ghost_src(i, g.n[0], g.bc_lo[0], g.bc_hi[0], fx);
+    int sj = ghost_src(j, g.n[1], g.bc_lo[1], g.bc_hi[1], fy);
+    int sk = ghost_src(k, g.n[2], g.bc_lo[2], g.bc_hi[2], fz);
+    const long long dst = cell(g, i, j, k), src = cell(g, si, sj, sk);
+    U[dst] = U[src];
+    double mu = U[g.cs + src], mv = U[2 * g.cs + src], mw = U[3 * g.cs + src];
+    U[g.cs + dst] = fx ? -mu : mu;
+    U[2 * g.cs + dst] = fy ? -mv : mv;
+    U[3 * g.cs + dst] = fz ? -mw : mw;
+    U[4 * g.cs + dst] = U[4 * g.cs + src];
+}
+
+// ---------------------------------------------------------------- dt
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = dmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cfl,
+                                               unsigned long long *dt_bits,
+                                               unsigned long long *dtmin_bits)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    const double *U = o.U;
+    const double gm1 = gamma - 1.0;
+    const long long nvalid = (long long)g.n[0] * g.n[1] * g.n[2];
+    double m = __longlong_as_double(0x7FF0000000000000LL);
+    for (long long t = o.blk * kBlock + threadIdx.x; t < nvalid; t += o.nblk * kBlock) {
+        int i = (int)(t % g.n[0]);
+        long long r = t / g.n[0];
+        int j = (int)(r % g.n[1]);
+        int k = (int)(r / g.n[1]);
+        long long c0 = cell(g, i, j, k);
+        Prim q = prim_of(U[c0], U[g.cs + c0], U[2 * g.cs + c0], U[3 * g.cs + c0],
+                         U[4 * g.cs + c0], gm1);
+        double c = sound(gamma, q.p, q.r);
+        double a = g.dx[0] / (fabs(q.u) + c);
+        double b = g.dx[1] / (fabs(q.v) + c);
+        double e = g.dx[2] / (fabs(q.w) + c);
+        m = dmin(m, dmin(dmin(a, b), e));
+    }
+    m = wave_min(m);
+    __shared__ double part[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = part[0];
+        for (int w = 1; w < kBlock / 64; ++w) b = dmin(b, part[w]);
+        // fl(cfl*x) is monotone in x, so the min of the scaled block minima
+        // is the scaled global minimum, bit for bit
+        unsigned long long v = (unsigned long long)__double_as_longlong(cfl * b);
+        atomicMin(dt_bits + o.b, v);
+        if (dtmin_bits) atomicMin(dtmin_bits, v);
+    }
+}
+
+// ---------------------------------------------------------------- prim
+
+__global__ void __launch_bounds__(kBlock) k_prim(Launch L, double gamma)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    long long t = o.blk * kBlock + threadIdx.x;
+    if (t >= g.cs) return;
+    const double *U = o.U;
+    Prim q = prim_of(U[t], U[g.cs + t], U[2 * g.cs + t], U[3 * g.cs + t], U[4 * g.cs + t],
+                     gamma - 1.0);
+    o.ws.f(P_R)[t] = q.r;
+    o.ws.f(P_U)[t] = q.u;
+    o.ws.f(P_V)[t] = q.v;
+    o.ws.f(P_W)[t] = q.w;
+    o.ws.f(P_P)[t] = q.p;
+    o.ws.f(P_C)[t] = sound(gamma, q.p, q.r);
+}
+
+// ---------------------------------------------------------------- trace
+
+__global__ void __launch_bounds__(kBlock) k_trace(Launch L, double gx, double gy, double gz)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    const int d = blockIdx.y;
+    int i, j, k;
+    if (!reg_cell(stage_reg(g, ST_TRACE), o.blk * kBlock + threadIdx.x, i, j, k)) return;
+    const WS &ws = o.ws;
+    const double dt = *o.dt;
+    const double dtdx = dt / g.dx[d];
+    const long long c0 = cell(g, i, j, k);
+    const long long sd = stride(g, d);
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const double *R = ws.f(P_R), *P = ws.f(P_P);
+    const double *Un = ws.f(P_U + d), *T1 = ws.f(P_U + t1), *T2 = ws.f(P_U + t2);
+    double rs[5], uns[5], t1s[5], t2s[5], ps[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        long long oo = c0 + (m - 2) * sd;
+        rs[m] = R[oo];
+        uns[m] = Un[oo];
+        t1s[m] = T1[oo];
+        t2s[m] = T2[oo];
+        ps[m] = P[oo];
+    }
+    Face hi, lo;
+    trace_cell(rs, uns, t1s, t2s, ps, ws.f(P_C)[c0], d, dtdx, hi, lo);
+    const double h = 0.5 * dt;
+    if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
+    if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
+    if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
+    ws.f(QHI(d, 0))[c0] = hi.r;
+    ws.f(QHI(d, 1))[c0] = hi.u;
+    ws.f(QHI(d, 2))[c0] = hi.v;
+    ws.f(QHI(d, 3))[c0] = hi.w;
+    ws.f(QHI(d, 4))[c0] = hi.p;
+    ws.f(QLO(d, 0))[c0] = lo.r;
+    ws.f(QLO(d, 1))[c0] = lo.u;
+    ws.f(QLO(d, 2))[c0] = lo.v;
+    ws.f(QLO(d, 3))[c0] = lo.w;
+    ws.f(QLO(d, 4))[c0] = lo.p;
+}
+
+__device__ __forceinline__ Face load_face(const WS &ws, int base, long long o)
+{
+    Face f;
+    f.r = ws.f(base + 0)[o];
+    f.u = ws.f(base + 1)[o];
+    f.v = ws.f(base + 2)[o];
+    f.w = ws.f(base + 3)[o];
+    f.p = ws.f(base + 4)[o];
+    return f;
+}
+
+__device__ __forceinline__ void store_flux(const WS &ws, int base, long long o, const Flux &F)
+{
+    ws.f(base + 0)[o] = F.m;
+    ws.f(base + 1)[o] = F.mu;
+    ws.f(base + 2)[o] = F.mv;
+    ws.f(base + 3)[o] = F.mw;
+    ws.f(base + 4)[o] = F.e;
+}
+
+// ---------------------------------------------------------------- flux1
+
+__global__ void __launch_bounds__(kBlock) k_flux1(Launch L, int d, double gamma)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    int i, j, k;
+    if (!reg_cell(stage_reg(g, ST_F1 + d), o.blk * kBlock + threadIdx.x, i, j, k)) return;
+    const long long c0 = cell(g, i, j, k);
+    Face Lf = load_face(o.ws, QHI(d, 0), c0 - stride(g, d));
+    Face Rf = load_face(o.ws, QLO(d, 0), c0);
+    store_flux(o.ws, F1F(d, 0), c0, hllc(Lf, Rf, d, gamma, gamma - 1.0));
+}
+
+// ---------------------------------------------------------------- flux2
+
+__device__ __forceinline__ Face corner(const WS &ws, const Face &q, int sd, long long oc,
+                                       long long ss, double fac, double gm1, int &err)
+{
+    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
+    const double *F0 = ws.f(F1F(sd, 0)), *F1 = ws.f(F1F(sd, 1)), *F2 = ws.f(F1F(sd, 2)),
+                 *F3 = ws.f(F1F(sd, 3)), *F4 = ws.f(F1F(sd, 4));
+    const long long oh = oc + ss;
+    double V0 = q.r - fac * (F0[oh] - F0[oc]);
+    double V1 = (q.r * q.u) - fac * (F1[oh] - F1[oc]);
+    double V2 = (q.r * q.v) - fac * (F2[oh] - F2[oc]);
+    double V3 = (q.r * q.w) - fac * (F3[oh] - F3[oc]);
+    double V4 = E - fac * (F4[oh] - F4[oc]);
+    return accept(q, V0, V1, V2, V3, V4, gm1, err);
+}
+
+__global__ void __launch_bounds__(kBlock) k_flux2(Launch L, int t, int sd, double gamma,
+                                                  int *err_dev)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    int i, j, k;
+    if (!reg_cell(stage_reg(g, ST_F2 + FAM(t, sd)), o.blk * kBlock + threadIdx.x, i, j, k))
+        return;
+    const double gm1 = gamma - 1.0;
+    const double fac = *o.dt / (3.0 * g.dx[sd]);
+    const long long c0 = cell(g, i, j, k);
+    const long long cl = c0 - stride(g, t);
+    const long long ss = stride(g, sd);
+    int err = 0;
+    Face qL = corner(o.ws, load_face(o.ws, QHI(t, 0), cl), sd, cl, ss, fac, gm1, err);
+    Face qR = corner(o.ws, load_face(o.ws, QLO(t, 0), c0), sd, c0, ss, fac, gm1, err);
+    store_flux(o.ws, F2F(FAM(t, sd), 0), c0, hllc(qL, qR, t, gamma, gm1));
+    if (err) atomicOr(err_dev, err);
+}
+
+// ---------------------------------------------------------------- flux3
+
+__device__ __forceinline__ Face final_state(const WS &ws, const Face &q, int fa, int fb,
+                                            long long oc, long long sa, long long sb,
+                                            double f1, double f2, double gm1, int &err)
+{
+    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
+    double U[5] = {q.r, q.r * q.u, q.r * q.v, q.r * q.w, E};
+    double V[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const double *A = ws.f(F2F(fa, v)), *B = ws.f(F2F(fb, v));
+        V[v] = (U[v] - f1 * (A[oc + sa] - A[oc])) - f2 * (B[oc + sb] - B[oc]);
+    }
+    return accept(q, V[0], V[1], V[2], V[3], V[4], gm1, err);
+}
+
+__global__ void __launch_bounds__(kBlock) k_flux3(Launch L, int d, double gamma, int *err_dev)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    int i, j, k;
+    if (!reg_cell(stage_reg(g, ST_F3 + d), o.blk * kBlock + threadIdx.x, i, j, k)) return;
+    const double gm1 = gamma - 1.0;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const double dt = *o.dt;
+    const double f1 = dt / (2.0 * g.dx[t1]);
+    const double f2 = dt / (2.0 * g.dx[t2]);
+    const long long c0 = cell(g, i, j, k);
+    const long long cl = c0 - stride(g, d);
+    const long long s1 = stride(g, t1), s2 = stride(g, t2);
+    const int fa = FAM(t1, t2), fb = FAM(t2, t1);
+    int err = 0;
+    Face qL = final_state(o.ws, load_face(o.ws, QHI(d, 0), cl), fa, fb, cl, s1, s2, f1, f2,
+                          gm1, err);
+    Face qR = final_state(o.ws, load_face(o.ws, QLO(d, 0), c0), fa, fb, c0, s1, s2, f1, f2,
+                          gm1, err);
+    store_flux(o.ws, F3F(d, 0), c0, hllc(qL, qR, d, gamma, gm1));
+    if (err) atomicOr(err_dev, err);
+}
+
+// ---------------------------------------------------------------- update
+
+__global__ void __launch_bounds__(kBlock) k_update(Launch L, double gamma, double gx,
+                                                   double gy, double gz, int *err_dev)
+{
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    int i, j, k;
+    if (!reg_cell(stage_reg(g, ST_UPD), o.blk * kBlock + threadIdx.x, i, j, k)) return;
+    const double gm1 = gamma - 1.0;
+    const double dt = *o.dt;
+    const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
+    const long long c0 = cell(g, i, j, k);
+    const long long sy = g.s[0], sz = (long long)g.s[0] * g.s[1];
+    double Uo[5], Us[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const double *X = o.ws.f(F3F(0, v)), *Y = o.ws.f(F3F(1, v)), *Z = o.ws.f(F3F(2, v));
+        double du = ax * (X[c0 + 1] - X[c0]);
+        du = du + ay * (Y[c0 + sy] - Y[c0]);
+        du = du + az * (Z[c0 + sz] - Z[c0]);
+        Uo[v] = o.U[v * g.cs + c0];
+        Us[v] = Uo[v] - du;
+    }
+    const double h = 0.5 * dt;
+    const double gg[3] = {gx, gy, gz};
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        if (gg[e] != 0.0) {
+            double hg = h * gg[e];
+            double mnew = Us[1 + e] + hg * (Uo[0] + Us[0]);
+            Us[4] = Us[4] + hg * (Uo[1 + e] + mnew);
+            Us[1 + e] = mnew;
+        }
+    int err = 0;
+    Prim q = prim_of(Us[0], Us[1], Us[2], Us[3], Us[4], gm1);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (!isfinite(Us[v])) err |= HYDRO_ERR_NONFINITE;
+        o.Un[v * g.cs + c0] = Us[v];
+    }
+    if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
+    if (q.p <= 0.0) err |= HYDRO_ERR_P;
+    if (err) atomicOr(err_dev, err);
+}
+
+// ---------------------------------------------------------------- host side
+
+bool box_valid(const hydro_box *b)
+{
+    if (!b || b->ng < 3 || b->ng > 8) return false;
+    for (int d = 0; d < 3; ++d) {
+        if (b->n[d] < 1 || b->n[d] > (1 << 20) || !(b->dx[d] > 0.0) || !isfinite(b->dx[d]))
+            return false;
+        for (int side = 0; side < 2; ++side) {
+            int bc = side ? b->bc_hi[d] : b->bc_lo[d];
+            if (bc < HYDRO_BC_PERIODIC || bc > HYDRO_BC_REFLECT) return false;
+            if (bc != HYDRO_BC_OUTFLOW && b->n[d] < b->ng) return false;
+        }
+        if ((b->bc_lo[d] == HYDRO_BC_PERIODIC) != (b->bc_hi[d] == HYDRO_BC_PERIODIC))
+            return false;
+    }
+    long long cs = 1;
+    for (int d = 0; d < 3; ++d) cs *= (long long)b->n[d] + 2 * b->ng;
+    // block indices are 32-bit: keep every stage of one box below 2^31 blocks
+    return cs < (1LL << 36);
+}
+
+bool params_valid(const hydro_params *p)
+{
+    return p && p->gamma > 1.0 && isfinite(p->gamma) && p->cfl > 0.0 && p->cfl <= 1.0 &&
+           isfinite(p->grav[0]) && isfinite(p->grav[1]) && isfinite(p->grav[2]);
+}
+
+Geo make_geo(const hydro_box *b)
+{
+    Geo g;
+    for (int d = 0; d < 3; ++d) {
+        g.n[d] = b->n[d];
+        g.s[d] = b->n[d] + 2 * b->ng;
+        g.dx[d] = b->dx[d];
+        g.bc_lo[d] = b->bc_lo[d];
+        g.bc_hi[d] = b->bc_hi[d];
+    }
+    g.ng = b->ng;
+    g.cs = (long long)g.s[0] * g.s[1] * g.s[2];
+    return g;
+}
+
+size_t box_ws_bytes(const Geo &g)
+{
+    size_t bytes = (size_t)kFields * (size_t)field_doubles(g.cs) * sizeof(double);
+    return (bytes + 255) / 256 * 256;
+}
+
+Launch single(const Geo &g, const double *U, double *Un, void *ws, const double *dt)
+{
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.g = g;
+    L.U = U;
+    L.Un = Un;
+    L.ws = (double *)ws;
+    L.dt = dt;
+    L.nb = 0;
+    return L;
+}
+
+// ---------------------------------------------------------------- profiling hook
+
+enum { PG_FILL, PG_DT, PG_PRIM, PG_TRACE, PG_FLUX1, PG_FLUX2, PG_FLUX3, PG_UPDATE, PG_COUNT };
+const char *const kPgNames[PG_COUNT] = {"fill", "dt", "prim", "trace",
+                                        "flux1", "flux2", "flux3", "update"};
+hipEvent_t g_ev[2 * PG_COUNT];
+bool g_ev_on = false;
+
+inline void prof(int group, int end, hipStream_t st)
+{
+    if (g_ev_on) (void)hipEventRecord(g_ev[2 * group + end], st);
+}
+
+hydro_status launch_status()
+{
+    return hipGetLastError() == hipSuccess ? HYDRO_OK : HYDRO_EHIP;
+}
+
+// the whole advance, given a launch template and per-stage grid sizes
+hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *const *pre,
+                             const hydro_params *prm, int32_t *err_dev, hipStream_t st)
+{
+    const double gamma = prm->gamma;
+    auto set = [&](int stage) {
+        if (L.nb) L.pre = pre[stage];
+        return dim3((unsigned)grid[stage]);
+    };
+    dim3 blk(kBlock);
+    prof(PG_PRIM, 0, st);
+    hipLaunchKernelGGL(k_prim, set(ST_PRIM), blk, 0, st, L, gamma);
+    prof(PG_PRIM, 1, st);
+    prof(PG_TRACE, 0, st);
+    {
+        dim3 gr = set(ST_TRACE);
+        gr.y = 3;
+        hipLaunchKernelGGL(k_trace, gr, blk, 0, st, L, prm->grav[0], prm->grav[1],
+                           prm->grav[2]);
+    }
+    prof(PG_TRACE, 1, st);
+    prof(PG_FLUX1, 0, st);
+    for (int d = 0; d < 3; ++d)
+        hipLaunchKernelGGL(k_flux1, set(ST_F1 + d), blk, 0, st, L, d, gamma);
+    prof(PG_FLUX1, 1, st);
+    prof(PG_FLUX2, 0, st);
+    for (int t = 0; t < 3; ++t)
+        for (int sd = 0; sd < 3; ++sd)
+            if (sd != t)
+                hipLaunchKernelGGL(k_flux2, set(ST_F2 + FAM(t, sd)), blk, 0, st, L, t, sd,
+                                   gamma, (int *)err_dev);
+    prof(PG_FLUX2, 1, st);
+    prof(PG_FLUX3, 0, st);
+    for (int d = 0; d < 3; ++d)
+        hipLaunchKernelGGL(k_flux3, set(ST_F3 + d), blk, 0, st, L, d, gamma, (int *)err_dev);
+    prof(PG_FLUX3, 1, st);
+    prof(PG_UPDATE, 0, st);
+    hipLaunchKernelGGL(k_update, set(ST_UPD), blk, 0, st, L, gamma, prm->grav[0],
+                       prm->grav[1], prm->grav[2], (int *)err_dev);
+    prof(PG_UPDATE, 1, st);
+    return launch_status();
+}
+
+// ---------------------------------------------------------------- plans
+
+struct Plan {
+    int nb;
+    std::vector<hydro_box> boxes;
+    std::vector<Geo> geos;
+    size_t ws_bytes;
+    long long grid[ST_COUNT];  // total blocks per stage
+    void *dev;                 // [Geo nb][long long wsoff nb][unsigned pre ST_COUNT x (nb+1)]
+    const Geo *geos_dev;
+    const long long *wsoff_dev;
+    const unsigned *pre_dev[ST_COUNT];
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t hydro_state_elems(const hydro_box *box)
+{
+    if (!box_valid(box)) return 0;
+    return (size_t)(5 * make_geo(box).cs);
+}
+
+size_t hydro_workspace_bytes(const hydro_box *boxes, int nboxes)
+{
+    if (!boxes || nboxes < 1) return 0;
+    size_t tot = 0;
+    for (int b = 0; b < nboxes; ++b) {
+        if (!box_valid(&boxes[b])) return 0;
+        tot += box_ws_bytes(make_geo(&boxes[b]));
+    }
+    return tot;
+}
+
+hydro_status hydro_fill_ghosts(double *U_dev, const hydro_box *box, void *stream)
+{
+    if (!U_dev || !box_valid(box)) return HYDRO_EINVAL;
+    Geo g = make_geo(box);
+    Launch L = single(g, U_dev, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)stage_blocks(g, ST_FILL)), dim3(kBlock), 0,
+                       (hipStream_t)stream, L, (unsigned long long *)nullptr,
+                       (unsigned long long *)nullptr);
+    return launch_status();
+}
+
+hydro_status estimate_dt(double *U_dev, const hydro_box *box, const hydro_params *prm,
+                         double *dt_dev, void *stream)
+{
+    if (!U_dev || !dt_dev || !box_valid(box) || !params_valid(prm)) return HYDRO_EINVAL;
+    Geo g = make_geo(box);
+    hipStream_t st = (hipStream_t)stream;
+    Launch L = single(g, U_dev, nullptr, nullptr, nullptr);
+    prof(PG_FILL, 0, st);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)stage_blocks(g, ST_FILL)), dim3(kBlock), 0, st,
+                       L, (unsigned long long *)dt_dev, (unsigned long long *)nullptr);
+    prof(PG_FILL, 1, st);
+    prof(PG_DT, 0, st);
+    hipLaunchKernelGGL(k_dt, dim3((unsigned)stage_blocks(g, ST_DT)), dim3(kBlock), 0, st, L,
+                       prm->gamma, prm->cfl, (unsigned long long *)dt_dev,
+                       (unsigned long long *)nullptr);
+    prof(PG_DT, 1, st);
+    return launch_status();
+}
+
+hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box *box,
+                         const hydro_params *prm, const double *dt_dev, void *ws_dev,
+                         size_t ws_bytes, int32_t *err_dev, void *stream)
+{
+    if (!U_dev || !U_new_dev || !dt_dev || !ws_dev || !err_dev || !box_valid(box) ||
+        !params_valid(prm))
+        return HYDRO_EINVAL;
+    if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
+    Geo g = make_geo(box);
+    {  // the new state must not overlap the old one
+        uintptr_t a0 = (uintptr_t)U_dev, a1 = a0 + 5 * g.cs * sizeof(double);
+        uintptr_t b0 = (uintptr_t)U_new_dev, b1 = b0 + 5 * g.cs * sizeof(double);
+        if (a0 < b1 && b0 < a1) return HYDRO_EINVAL;
+    }
+    if (ws_bytes < box_ws_bytes(g)) return HYDRO_ENOWS;
+    long long grid[ST_COUNT];
+    for (int s = 0; s < ST_COUNT; ++s) grid[s] = stage_blocks(g, s);
+    Launch L = single(g, U_dev, U_new_dev, ws_dev, dt_dev);
+    return enqueue_advance(L, grid, nullptr, prm, err_dev, (hipStream_t)stream);
+}
+
+hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,
+                               void **plan_out)
+{
+    (void)autotune_json;
+    if (!boxes || nb < 1 || !plan_out) return HYDRO_EINVAL;
+    *plan_out = nullptr;
+    Plan *P = new (std::nothrow) Plan();
+    if (!P) return HYDRO_EINVAL;
+    P->nb = nb;
+    P->boxes.assign(boxes, boxes + nb);
+    P->ws_bytes = 0;
+    std::vector<long long> wsoff(nb);
+    std::vector<unsigned> pre((size_t)ST_COUNT * (nb + 1));
+    for (int b = 0; b < nb; ++b) {
+        if (!box_valid(&boxes[b])) {
+            delete P;
+            return HYDRO_EINVAL;
+        }
+        Geo g = make_geo(&boxes[b]);
+        P->geos.push_back(g);
+        wsoff[b] = (long long)(P->ws_bytes / sizeof(double));
+        P->ws_bytes += box_ws_bytes(g);
+    }
+    for (int s = 0; s < ST_COUNT; ++s) {
+        unsigned long long acc = 0;
+        for (int b = 0; b < nb; ++b) {
+            pre[(size_t)s * (nb + 1) + b] = (unsigned)acc;
+            acc += (unsigned long long)stage_blocks(P->geos[b], s);
+        }
+        if (acc >= (1ULL << 31)) {
+            delete P;
+            return HYDRO_EINVAL;
+        }
+        pre[(size_t)s * (nb + 1) + nb] = (unsigned)acc;
+        P->grid[s] = (long long)acc;
+    }
+    size_t szg = sizeof(Geo) * nb, szw = sizeof(long long) * nb,
+           szp = sizeof(unsigned) * pre.size();
+    size_t offw = (szg + 255) / 256 * 256, offp = offw + (szw + 255) / 256 * 256;
+    if (hipMalloc(&P->dev, offp + szp) != hipSuccess) {
+        delete P;
+        return HYDRO_EHIP;
+    }
+    char *base = (char *)P->dev;
+    if (hipMemcpy(base, P->geos.data(), szg, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + offw, wsoff.data(), szw, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + offp, pre.data(), szp, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(P->dev);
+        delete P;
+        return HYDRO_EHIP;
+    }
+    P->geos_dev = (const Geo *)base;
+    P->wsoff_dev = (const long long *)(base + offw);
+    for (int s = 0; s < ST_COUNT; ++s)
+        P->pre_dev[s] = (const unsigned *)(base + offp) + (size_t)s * (nb + 1);
+    *plan_out = P;
+    return HYDRO_OK;
+}
+
+void hydro_plan_destroy(void *plan)
+{
+    Plan *P = (Plan *)plan;
+    if (!P) return;
+    if (P->dev) (void)hipFree(P->dev);
+    delete P;
+}
+
+static Launch batch_launch(const Plan *P, double *const *Us, double *const *Uns, void *ws,
+                           const double *dts, int dt_stride)
+{
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.nb = P->nb;
+    L.geos = P->geos_dev;
+    L.Us = Us;
+    L.Uns = Uns;
+    L.ws = (double *)ws;
+    L.wsoff = P->wsoff_dev;
+    L.dts = dts;
+    L.dt_stride = dt_stride;
+    return L;
+}
+
+hydro_status estimate_dt_boxes(int nb, double *const *U_ptrs_dev, const void *plan,
+                               const hydro_params *prm, double *dt_dev, double *dt_min_dev,
+                               void *stream)
+{
+    const Plan *P = (const Plan *)plan;
+    if (!P || nb != P->nb || !U_ptrs_dev || !dt_dev || !params_valid(prm))
+        return HYDRO_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Launch L = batch_launch(P, U_ptrs_dev, nullptr, nullptr, nullptr, 0);
+    L.pre = P->pre_dev[ST_FILL];
+    prof(PG_FILL, 0, st);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)P->grid[ST_FILL]), dim3(kBlock), 0, st, L,
+                       (unsigned long long *)dt_dev, (unsigned long long *)dt_min_dev);
+    prof(PG_FILL, 1, st);
+    L.pre = P->pre_dev[ST_DT];
+    prof(PG_DT, 0, st);
+    hipLaunchKernelGGL(k_dt, dim3((unsigned)P->grid[ST_DT]), dim3(kBlock), 0, st, L,
+                       prm->gamma, prm->cfl, (unsigned long long *)dt_dev,
+                       (unsigned long long *)dt_min_dev);
+    prof(PG_DT, 1, st);
+    return launch_status();
+}
+
+hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
+                           double *const *U_new_ptrs_dev, const void *plan,
+                           const hydro_params *prm, const double *dt_dev, int dt_stride,
+                           void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream)
+{
+    const Plan *P = (const Plan *)plan;
+    if (!P || nb != P->nb || !U_ptrs_dev || !U_new_ptrs_dev || !dt_dev || !ws_dev ||
+        !err_dev || !params_valid(prm) || (dt_stride != 0 && dt_stride != 1))
+        return HYDRO_EINVAL;
+    if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
+    if (ws_bytes < P->ws_bytes) return HYDRO_ENOWS;
+    Launch L = batch_launch(P, (double *const *)U_ptrs_dev, U_new_ptrs_dev, ws_dev, dt_dev,
+                            dt_stride);
+    return enqueue_advance(L, P->grid, P->pre_dev, prm, err_dev, (hipStream_t)stream);
+}
+
+int hydro_stage_count(void) { return PG_COUNT; }
+
+const char *hydro_stage_name(int s) { return (s >= 0 && s < PG_COUNT) ? kPgNames[s] : ""; }
+
+hydro_status hydro_set_stage_events(void *const *events)
+{
+    if (!events) {
+        g_ev_on = false;
+        return HYDRO_OK;
+    }
+    for (int i = 0; i < 2 * PG_COUNT; ++i)
+        if (!events[i]) return HYDRO_EINVAL;
+    for (int i = 0; i < 2 * PG_COUNT; ++i) g_ev[i] = (hipEvent_t)events[i];
+    g_ev_on = true;
+    return HYDRO_OK;
+}
+
+const char *hydro_status_string(hydro_status s)
+{
+    switch (s) {
+    case HYDRO_OK: return "HYDRO_OK";
+    case HYDRO_EINVAL: return "HYDRO_EINVAL: invalid argument";
+    case HYDRO_EHIP: return "HYDRO_EHIP: HIP runtime or launch failure";
+    case HYDRO_ENOWS: return "HYDRO_ENOWS: workspace too small";
+    }
+    return "unknown hydro_status";
+}
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+"""Python binding of the C ABI in include/hydro.h (argument marshalling only).
+
+Every function here forwards to ``libhydro.so``; all arithmetic of the hydro
+step runs in its HIP kernels.  PyTorch provides device memory and streams:
+state arrays are CUDA float64 tensors of shape (5, n2+2ng, n1+2ng, n0+2ng)
+(see inputs.state_shape), timesteps and error words are small device
+tensors, and every call is enqueued on torch's current stream unless a
+stream is given.
+
+There is no CPU fallback: importing this module without the built library,
+or calling it without a GPU, raises.
+"""
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+
+HYDRO_OK, HYDRO_EINVAL, HYDRO_EHIP, HYDRO_ENOWS = 0, 1, 2, 3
+ERR_NONFINITE, ERR_RHO, ERR_P, ERR_FALLBACK = 1, 2, 4, 8
+
+EXPORTS = ("hydro_state_elems", "hydro_workspace_bytes", "hydro_fill_ghosts", "estimate_dt",
+           "advance_box", "estimate_dt_boxes", "advance_boxes", "hydro_plan_create",
+           "hydro_plan_destroy", "hydro_status_string", "hydro_stage_count",
+           "hydro_stage_name", "hydro_set_stage_events")
+
+
+class HydroBox(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("ng", C.c_int32), ("dx", C.c_double * 3),
+                ("bc_lo", C.c_int32 * 3), ("bc_hi", C.c_int32 * 3)]
+
+
+class HydroParams(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("grav", C.c_double * 3)]
+
+
+class HydroError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        msg = lib().hydro_status_string(status).decode()
+        super().__init__("%s: %s" % (fn, msg))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhydro.so is not built: run paper_2007_05218_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        bp = C.POINTER(HydroBox)
+        pp = C.POINTER(HydroParams)
+        L.hydro_state_elems.argtypes = [bp]
+        L.hydro_state_elems.restype = C.c_size_t
+        L.hydro_workspace_bytes.argtypes = [bp, C.c_int]
+        L.hydro_workspace_bytes.restype = C.c_size_t
+        L.hydro_fill_ghosts.argtypes = [vp, bp, vp]
+        L.estimate_dt.argtypes = [vp, bp, pp, vp, vp]
+        L.advance_box.argtypes = [vp, vp, bp, pp, vp, vp, C.c_size_t, vp, vp]
+        L.estimate_dt_boxes.argtypes = [C.c_int, vp, vp, pp, vp, vp, vp]
+        L.advance_boxes.argtypes = [C.c_int, vp, vp, vp, pp, vp, C.c_int, vp, C.c_size_t,
+                                    vp, vp]
+        L.hydro_plan_create.argtypes = [bp, C.c_int, C.c_char_p, C.POINTER(vp)]
+        L.hydro_plan_destroy.argtypes = [vp]
+        L.hydro_plan_destroy.restype = None
+        L.hydro_stage_count.argtypes = []
+        L.hydro_stage_count.restype = C.c_int
+        L.hydro_stage_name.argtypes = [C.c_int]
+        L.hydro_stage_name.restype = C.c_char_p
+        L.hydro_set_stage_events.argtypes = [C.POINTER(vp)]
+        L.hydro_set_stage_events.restype = C.c_int
+        L.hydro_status_string.argtypes = [C.c_int]
+        L.hydro_status_string.restype = C.c_char_p
+        for f in ("hydro_fill_ghosts", "estimate_dt", "advance_box", "estimate_dt_boxes",
+                  "advance_boxes", "hydro_plan_create"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(fn, st):
+    if st != HYDRO_OK:
+        raise HydroError(fn, st)
+
+
+def make_box(desc):
+    """HydroBox from a box description dict (inputs.box_desc)."""
+    return HydroBox((C.c_int32 * 3)(*desc["n"]), desc["ng"], (C.c_double * 3)(*desc["dx"]),
+                    (C.c_int32 * 3)(*desc["bc_lo"]), (C.c_int32 * 3)(*desc["bc_hi"]))
+
+
+def make_params(desc):
+    return HydroParams(desc["gamma"], desc["cfl"], (C.c_double * 3)(*desc["grav"]))
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, dtype=torch.float64):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA %s tensor" % dtype)
+    return C.c_void_p(t.data_ptr())
+
+
+def state_elems(box):
+    return int(lib().hydro_state_elems(C.byref(make_box(box))))
+
+
+def workspace_bytes(boxes):
+    if isinstance(boxes, dict):
+        boxes = [boxes]
+    arr = (HydroBox * len(boxes))(*[make_box(b) for b in boxes])
+    return int(lib().hydro_workspace_bytes(arr, len(boxes)))
+
+
+def _check_state(U, box):
+    if U.numel() != state_elems(box):
+        raise ValueError("state tensor has %d elements, box needs %d"
+                         % (U.numel(), state_elems(box)))
+
+
+def fill_ghosts(U, box, stream=None):
+    _check_state(U, box)
+    _check("hydro_fill_ghosts", lib().hydro_fill_ghosts(_ptr(U), C.byref(make_box(box)),
+                                                        _stream(stream)))
+
+
+def estimate_dt(U, box, prm, dt, stream=None):
+    """Fill U's ghosts and write the CFL timestep to the 1-element device tensor dt."""
+    _check_state(U, box)
+    _check("estimate_dt", lib().estimate_dt(_ptr(U), C.byref(make_box(box)),
+                                            C.byref(make_params(prm)), _ptr(dt),
+                                            _stream(stream)))
+
+
+def advance_box(U, Unew, box, prm, dt, ws, err, stream=None):
+    """One step of length dt[0] from U (ghosts filled) into the valid cells of Unew."""
+    _check_state(U, box)
+    _check_state(Unew, box)
+    _check("advance_box", lib().advance_box(_ptr(U), _ptr(Unew), C.byref(make_box(box)),
+                                            C.byref(make_params(prm)), _ptr(dt),
+                                            _ptr(ws, torch.uint8), ws.numel(),
+                                            _ptr(err, torch.int32), _stream(stream)))
+
+
+def alloc_workspace(boxes, device="cuda"):
+    return torch.empty(max(workspace_bytes(boxes), 256), dtype=torch.uint8, device=device)
+
+
+class Box:
+    """A single box on the GPU: state ping-pong buffers, workspace, dt and error
+    words, all device-resident; ``step()`` enqueues one whole step
+    (ghost fill + dt + advance) with no host synchronisation."""
+
+    def __init__(self, U_host, box, prm, device="cuda"):
+        self.box = dict(box)
+        self.prm = dict(prm)
+        self.U = torch.as_tensor(U_host, dtype=torch.float64).to(device).contiguous()
+        self.Unew = torch.empty_like(self.U)
+        self.ws = alloc_workspace(self.box, device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        self.err = torch.zeros(1, dtype=torch.int32, device=device)
+        self.t = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def step(self, stream=None):
+        estimate_dt(self.U, self.box, self.prm, self.dt, stream)
+        advance_box(self.U, self.Unew, self.box, self.prm, self.dt, self.ws, self.err, stream)
+        self.U, self.Unew = self.Unew, self.U
+
+    def run(self, steps, stream=None):
+        for _ in range(steps):
+            self.step(stream)
+
+    def state(self):
+        """Host copy of the current state (ghosts as last filled)."""
+        return self.U.cpu().numpy()
+
+
+class Plan:
+    """A plan for a fixed list of boxes (hydro_plan_create): validated boxes,
+    per-stage work lists on the device.  Owns one small device buffer."""
+
+    def __init__(self, boxes, autotune_json=None):
+        self.boxes = [dict(b) for b in boxes]
+        arr = (HydroBox * len(boxes))(*[make_box(b) for b in boxes])
+        h = C.c_void_p()
+        js = autotune_json.encode() if autotune_json else None
+        _check("hydro_plan_create", lib().hydro_plan_create(arr, len(boxes), js, C.byref(h)))
+        self.handle = h
+        self.nb = len(boxes)
+        self.ws_bytes = workspace_bytes(self.boxes)
+
+    def close(self):
+        if self.handle:
+            lib().hydro_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pointer_array(tensors, device="cuda"):
+    """Device int64 tensor holding the data pointers of ``tensors``."""
+    return torch.tensor([t.data_ptr() for t in tensors], dtype=torch.int64, device=device)
+
+
+def estimate_dt_boxes(plan, U_ptrs, prm, dt, dt_min=None, stream=None):
+    """Fill every box's ghosts; dt[b] = box b's CFL step; dt_min[0] = min over boxes."""
+    _check("estimate_dt_boxes", lib().estimate_dt_boxes(
+        plan.nb, _ptr(U_ptrs, torch.int64), plan.handle, C.byref(make_params(prm)), _ptr(dt),
+        _ptr(dt_min) if dt_min is not None else None, _stream(stream)))
+
+
+def advance_boxes(plan, U_ptrs, Unew_ptrs, prm, dt, ws, err, dt_stride=1, stream=None):
+    """Advance every box of the plan by dt[b] (dt_stride=1) or dt[0] (dt_stride=0)."""
+    _check("advance_boxes", lib().advance_boxes(
+        plan.nb, _ptr(U_ptrs, torch.int64), _ptr(Unew_ptrs, torch.int64), plan.handle,
+        C.byref(make_params(prm)), _ptr(dt), dt_stride, _ptr(ws, torch.uint8), ws.numel(),
+        _ptr(err, torch.int32), _stream(stream)))
+
+
+class Level:
+    """A list of independent boxes advanced together (a level of boxes): states
+    and workspace on the device, one launch per stage for all boxes.
+    ``shared_dt`` advances every box by the level-wide minimum timestep."""
+
+    def __init__(self, states, boxes, prm, shared_dt=True, device="cuda", autotune_json=None):
+        self.prm = dict(prm)
+        self.plan = Plan(boxes, autotune_json)
+        self.U = [torch.as_tensor(u, dtype=torch.float64).to(device).contiguous() for u in states]
+        self.Unew = [torch.empty_like(u) for u in self.U]
+        self.pa = pointer_array(self.U, device)
+        self.pb = pointer_array(self.Unew, device)
+        self.ws = torch.empty(max(self.plan.ws_bytes, 256), dtype=torch.uint8, device=device)
+        self.dt = torch.zeros(len(states), dtype=torch.float64, device=device)
+        self.dt_min = torch.zeros(1, dtype=torch.float64, device=device)
+        self.err = torch.zeros(1, dtype=torch.int32, device=device)
+        self.shared_dt = shared_dt
+
+    def step(self, stream=None):
+        estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, self.dt_min, stream)
+        if self.shared_dt:
+            advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt_min, self.ws, self.err,
+                          dt_stride=0, stream=stream)
+        else:
+            advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt, self.ws, self.err,
+                          dt_stride=1, stream=stream)
+        self.U, self.Unew = self.Unew, self.U
+        self.pa, self.pb = self.pb, self.pa
+
+    def run(self, steps, stream=None):
+        for _ in range(steps):
+            self.step(stream)
+
+    def states(self):
+        return [u.cpu().numpy() for u in self.U]
+
+
+class StageTimer:
+    """Per-stage device time of library calls (hydro_set_stage_events): wrap
+    each profiled call in ``with timer:``; totals accumulate in ms per stage."""
+
+    def __init__(self):
+        L = lib()
+        self.names = [L.hydro_stage_name(s).decode() for s in range(L.hydro_stage_count())]
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(self.names))]
+        s = torch.cuda.current_stream()
+        for e in self.events:  # torch creates the HIP event on first record
+            e.record(s)
+        torch.cuda.synchronize()
+        self.total_ms = {n: 0.0 for n in self.names}
+        self.calls = 0
+
+    def __enter__(self):
+        for e in self.events:
+            e.record()
+        torch.cuda.synchronize()
+        arr = (C.c_void_p * len(self.events))(*[e.cuda_event for e in self.events])
+        _check("hydro_set_stage_events", lib().hydro_set_stage_events(arr))
+        return self
+
+    def __exit__(self, *exc):
+        lib().hydro_set_stage_events(None)
+        torch.cuda.synchronize()
+        for i, n in enumerate(self.names):
+            a, b = self.events[2 * i], self.events[2 * i + 1]
+            ms = a.elapsed_time(b)
+            if ms > 0:
+                self.total_ms[n] += ms
+        self.calls += 1
+        return False

@@ -155,7 +155,8 @@ def smooth(n, seed, dx=None, ng=NG):
     box = box_desc(nn, ng, dx=dx, bc_lo=(BC_PERIODIC,) * 3)
     L = [nn[d] * box["dx"][d] for d in range(3)]
     xyz = cell_centres(box)
-    kids = np.random.SeedSequence(seed).spawn(5)
+    ss = seed if isinstance(seed, np.random.SeedSequence) else np.random.SeedSequence(seed)
+    kids = ss.spawn(5)
     fields = [_modes(np.random.default_rng(s), nn, L, xyz) for s in kids]
     shp = (nn[2], nn[1], nn[0])
     rho = np.broadcast_to(1.25 + 0.75 * fields[0], shp)

@@ -1,0 +1,108 @@
+"""The C ABI library: it loads, exports every entry point include/hydro.h
+declares, and validates arguments synchronously (no GPU needed; no call
+here launches a kernel)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2007_05218_amd import hydro, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hydro.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\(", src)
+    skip = {"defined", "sizeof"}
+    return sorted({n for n in names if n not in skip and not n.isupper()})
+
+
+def test_library_exports_every_declared_symbol():
+    L = hydro.lib()
+    decl = _declared()
+    assert set(decl) == set(hydro.EXPORTS), decl
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts():
+    assert C.sizeof(hydro.HydroBox) == 64
+    assert C.sizeof(hydro.HydroParams) == 40
+    assert hydro.HydroBox.dx.offset == 16
+    assert hydro.HydroBox.bc_lo.offset == 40
+
+
+def test_state_and_workspace_sizes():
+    U, box, prm = inputs.sod(32)
+    assert hydro.state_elems(box) == U.size == 5 * 40 ** 3
+    ws = hydro.workspace_bytes(box)
+    assert ws >= 96 * 40 ** 3 * 8 and ws % 256 == 0
+    boxes = [inputs.box_desc((16, 32, 64)), inputs.box_desc((64, 16, 16))]
+    assert hydro.workspace_bytes(boxes) == sum(hydro.workspace_bytes(b) for b in boxes)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=(0, 8, 8)), dict(ng=2), dict(ng=9), dict(dx=(0.0, 1.0, 1.0)),
+    dict(n=(3, 8, 8), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0)),  # periodic axis shorter than ng
+    dict(bc_lo=(0, 1, 1), bc_hi=(1, 1, 1)),               # unpaired periodic
+    dict(bc_lo=(5, 1, 1), bc_hi=(5, 1, 1)),
+])
+def test_invalid_boxes_rejected(bad):
+    d = inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1))
+    d.update(bad)
+    assert hydro.state_elems(d) == 0
+    assert hydro.workspace_bytes(d) == 0
+    L = hydro.lib()
+    b = hydro.make_box(d)
+    p = hydro.make_params(inputs.params_desc())
+    fake = C.c_void_p(256)
+    assert L.estimate_dt(fake, C.byref(b), C.byref(p), fake, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_fill_ghosts(fake, C.byref(b), None) == hydro.HYDRO_EINVAL
+    assert L.advance_box(fake, C.c_void_p(1 << 40), C.byref(b), C.byref(p), fake, fake,
+                         1 << 40, fake, None) == hydro.HYDRO_EINVAL
+    arr = (hydro.HydroBox * 1)(b)
+    h = C.c_void_p()
+    assert L.hydro_plan_create(arr, 1, None, C.byref(h)) == hydro.HYDRO_EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(cfl=0.0), dict(cfl=1.5),
+                                 dict(gamma=float("nan"))])
+def test_invalid_params_rejected(bad):
+    d = inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1))
+    p = inputs.params_desc()
+    p.update(bad)
+    L = hydro.lib()
+    fake = C.c_void_p(256)
+    assert L.estimate_dt(fake, C.byref(hydro.make_box(d)), C.byref(hydro.make_params(p)),
+                         fake, None) == hydro.HYDRO_EINVAL
+
+
+def test_null_and_overlap_rejected():
+    d = inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1))
+    L = hydro.lib()
+    b = hydro.make_box(d)
+    p = hydro.make_params(inputs.params_desc())
+    a = C.c_void_p(1 << 30)
+    ws = C.c_void_p(1 << 34)
+    nbytes = hydro.workspace_bytes(d)
+    # U_new overlapping U
+    assert L.advance_box(a, C.c_void_p((1 << 30) + 8), C.byref(b), C.byref(p), a, ws, nbytes,
+                         a, None) == hydro.HYDRO_EINVAL
+    # workspace misaligned
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), a,
+                         C.c_void_p((1 << 34) + 8), nbytes, a, None) == hydro.HYDRO_EINVAL
+    # workspace too small
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), a, ws, nbytes - 256,
+                         a, None) == hydro.HYDRO_ENOWS
+    assert L.estimate_dt(None, C.byref(b), C.byref(p), a, None) == hydro.HYDRO_EINVAL
+    assert L.advance_boxes(1, a, a, None, C.byref(p), a, 1, ws, nbytes, a,
+                           None) == hydro.HYDRO_EINVAL
+
+
+def test_status_strings():
+    L = hydro.lib()
+    for s in range(4):
+        assert L.hydro_status_string(s).startswith(b"HYDRO_")

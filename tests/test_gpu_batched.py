@@ -1,0 +1,92 @@
+"""Batched level (advance_boxes): every box matches the oracle and matches its
+own single-box advance bitwise, with a shared (level-wide) or per-box dt."""
+import numpy as np
+import pytest
+
+from parity import compare
+from paper_2007_05218_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2007_05218_amd import hydro
+    hydro.lib()
+    return hydro
+
+
+def _oracle_level(orc, states, boxes, prm, steps, shared=True):
+    states = [u.copy() for u in states]
+    obs = [orc.box_from(b) for b in boxes]
+    op = orc.params_from(prm)
+    err = 0
+    for _ in range(steps):
+        dts = []
+        for U, ob in zip(states, obs):
+            orc.fill_ghosts(U, ob)
+            dts.append(orc.estimate_dt(U, ob, op))
+        dmin = min(dts)
+        new = []
+        for U, ob, dt in zip(states, obs, dts):
+            Un = U.copy()
+            err |= orc.advance_box(U, Un, ob, op, dmin if shared else dt)
+            new.append(Un)
+        states = new
+    return states, err
+
+
+@pytest.mark.parametrize("shared", [True, False])
+def test_level_matches_oracle(gpu, orc, shared):
+    import torch
+    states, boxes, prm = inputs.level(nboxes=24, seed=5)
+    lev = gpu.Level(states, boxes, prm, shared_dt=shared)
+    lev.run(20)
+    torch.cuda.synchronize()
+    gs = lev.states()
+    os_, oerr = _oracle_level(orc, states, boxes, prm, 20, shared)
+    assert int(lev.err.item()) == oerr
+    for g, o, b in zip(gs, os_, boxes):
+        err, bw = compare(inputs.valid(g, b), inputs.valid(o, b))
+        assert err <= TOL and bw == 1.0, (b["n"], err, bw)
+
+
+def test_full_level_batched_equals_per_box(gpu, orc):
+    # the 512-box level: one batched step == 512 single-box steps, bitwise;
+    # a few boxes also against the oracle
+    import torch
+    states, boxes, prm = inputs.level(nboxes=512, seed=2)
+    lev = gpu.Level(states, boxes, prm, shared_dt=True)
+    lev.step()
+    torch.cuda.synchronize()
+    dmin = lev.dt_min.item()
+    per = lev.dt.cpu().numpy()
+    gs = lev.states()
+    assert dmin == per.min()
+    dt = torch.tensor([dmin], dtype=torch.float64, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for b in range(len(boxes)):
+        U = torch.tensor(states[b], device="cuda")
+        Un = torch.empty_like(U)
+        d1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gpu.estimate_dt(U, boxes[b], prm, d1)
+        ws = gpu.alloc_workspace(boxes[b])
+        gpu.advance_box(U, Un, boxes[b], prm, dt, ws, err)
+        torch.cuda.synchronize()
+        assert d1.item() == per[b]
+        assert np.array_equal(inputs.valid(Un.cpu().numpy(), boxes[b]),
+                              inputs.valid(gs[b], boxes[b])), b
+    assert int(err.item()) == int(lev.err.item())
+    op = orc.params_from(prm)
+    for b in [0, 17, 255, 511]:
+        U = states[b].copy()
+        ob = orc.box_from(boxes[b])
+        orc.fill_ghosts(U, ob)
+        Un = U.copy()
+        orc.advance_box(U, Un, ob, op, dmin)
+        e, bw = compare(inputs.valid(gs[b], boxes[b]), inputs.valid(Un, boxes[b]))
+        assert e <= TOL and bw == 1.0
