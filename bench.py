@@ -16,9 +16,11 @@ Also reported on the same JSON line:
                 against the FP64 VALU issue peak of the chip
   cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
                 same workload (rank 0, N = 1 only)
-  also          secondary workloads: the 256^3 Kelvin-Helmholtz box, and the
+  also          secondary workloads: the 256^3 Kelvin-Helmholtz box; the
                 512-box batched level (one launch per stage for all boxes)
-                against the same boxes launched one by one
+                against the same boxes launched one by one; the serving loop
+                (p50/p99 latency and cell-updates/s at 80% load, and its
+                saturated capacity batched vs one request at a time)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads ...]
 """
@@ -47,8 +49,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="rt512,kh256,level",
-                    help="comma list of rt512, kh256, level")
+    ap.add_argument("--workloads", default="rt512,kh256,level,serve",
+                    help="comma list of rt512, kh256, level, serve")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--level-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -127,6 +131,35 @@ def time_level(hydro, torch, inputs, steps, warmup):
             "batched_cu_per_s": cells * steps / (ms_batched * 1e-3),
             "per_box_cu_per_s": cells * steps / (ms_per_box * 1e-3),
             "batched_ms_per_step": ms_batched / steps, "per_box_ms_per_step": ms_per_box / steps}
+
+
+def time_serving(inputs, nreq, warm, seed=3):
+    """Continuous-batching server: saturated capacity (all requests at t=0),
+    the same with one request at a time, then a Poisson stream at 80% load."""
+    from paper_2007_05218_amd.serve import GpuExecutor, Server
+    import numpy as np
+    probe = inputs.request_stream(24, rate=0.0, seed=seed + 100)
+    for s in probe:
+        s["arrival"] = 0.0
+    cap = {}
+    for name, slots in (("batched", 64), ("one_at_a_time", 1)):
+        srv = Server(GpuExecutor(), budget_bytes=200e9, max_active=slots)
+        srv.run(probe)
+        cap[name] = srv.metrics()["cu_per_s"]
+    sample = inputs.request_stream(20000, rate=1.0, seed=seed + 1)
+    ework = float(np.mean([r["n"] ** 3 * r["steps"] for r in sample]))
+    lam = 0.8 * cap["batched"] / ework
+    specs = inputs.request_stream(nreq, rate=lam, seed=seed)
+    srv = Server(GpuExecutor(), budget_bytes=200e9, max_active=64)
+    srv.run(specs)
+    m = srv.metrics(skip=warm)
+    m.update({"workload": "serve: Poisson arrivals at 80%% of saturated capacity, cubic n "
+                          "log-uniform in [32,192], steps uniform in [10,200], families "
+                          "sod/kh/smooth, 200 GB HBM budget, seed %d" % seed,
+              "rate_per_s": lam, "mean_work_cu": ework, "warmup_requests": warm,
+              "capacity_batched_cu_per_s": cap["batched"],
+              "capacity_one_at_a_time_cu_per_s": cap["one_at_a_time"]})
+    return m
 
 
 def cpu_baseline(inputs, U, box, prm, seconds):
@@ -218,6 +251,10 @@ def main():
     if "level" in work:
         log("timing the 512-box level, batched vs per-box")
         also["level512"] = time_level(hydro, torch, inputs, args.level_steps, 1)
+    if "serve" in work:
+        log("serving %d requests" % args.serve_requests)
+        also["serve"] = time_serving(inputs, args.serve_requests, args.serve_warmup)
+        log("serve:", json.dumps(also["serve"]))
 
     out = {"metric": "FP64 hydro cell-updates/s (whole step: ghost fill + CFL dt + CTU-PPM-HLLC advance)",
            "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,

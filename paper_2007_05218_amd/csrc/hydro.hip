@@ -374,11 +374,14 @@ __global__ void __launch_bounds__(kBlock) k_prim(Launch L, double gamma)
 
 // ---------------------------------------------------------------- trace
 
-__global__ void __launch_bounds__(kBlock) k_trace(Launch L, double gx, double gy, double gz)
+// every direction index below is a compile-time constant, so the box
+// descriptor stays in registers (a runtime index into it would put the
+// descriptor in per-lane scratch memory)
+template <int d>
+__device__ __forceinline__ void trace_body(const Launch &L, double gx, double gy, double gz)
 {
     Box1 o = resolve(L);
     const Geo &g = o.g;
-    const int d = blockIdx.y;
     int i, j, k;
     if (!reg_cell(stage_reg(g, ST_TRACE), o.blk * kBlock + threadIdx.x, i, j, k)) return;
     const WS &ws = o.ws;
@@ -417,6 +420,13 @@ __global__ void __launch_bounds__(kBlock) k_trace(Launch L, double gx, double gy
     ws.f(QLO(d, 4))[c0] = lo.p;
 }
 
+__global__ void __launch_bounds__(kBlock) k_trace(Launch L, double gx, double gy, double gz)
+{
+    if (blockIdx.y == 0) trace_body<0>(L, gx, gy, gz);
+    else if (blockIdx.y == 1) trace_body<1>(L, gx, gy, gz);
+    else trace_body<2>(L, gx, gy, gz);
+}
+
 __device__ __forceinline__ Face load_face(const WS &ws, int base, long long o)
 {
     Face f;
@@ -439,7 +449,8 @@ __device__ __forceinline__ void store_flux(const WS &ws, int base, long long o, 
 
 // ---------------------------------------------------------------- flux1
 
-__global__ void __launch_bounds__(kBlock) k_flux1(Launch L, int d, double gamma)
+template <int d>
+__global__ void __launch_bounds__(kBlock) k_flux1(Launch L, double gamma)
 {
     Box1 o = resolve(L);
     const Geo &g = o.g;
@@ -468,8 +479,8 @@ __device__ __forceinline__ Face corner(const WS &ws, const Face &q, int sd, long
     return accept(q, V0, V1, V2, V3, V4, gm1, err);
 }
 
-__global__ void __launch_bounds__(kBlock) k_flux2(Launch L, int t, int sd, double gamma,
-                                                  int *err_dev)
+template <int t, int sd>
+__global__ void __launch_bounds__(kBlock) k_flux2(Launch L, double gamma, int *err_dev)
 {
     Box1 o = resolve(L);
     const Geo &g = o.g;
@@ -505,7 +516,8 @@ __device__ __forceinline__ Face final_state(const WS &ws, const Face &q, int fa,
     return accept(q, V[0], V[1], V[2], V[3], V[4], gm1, err);
 }
 
-__global__ void __launch_bounds__(kBlock) k_flux3(Launch L, int d, double gamma, int *err_dev)
+template <int d>
+__global__ void __launch_bounds__(kBlock) k_flux3(Launch L, double gamma, int *err_dev)
 {
     Box1 o = resolve(L);
     const Geo &g = o.g;
@@ -657,8 +669,9 @@ hydro_status launch_status()
 
 // the whole advance, given a launch template and per-stage grid sizes
 hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *const *pre,
-                             const hydro_params *prm, int32_t *err_dev, hipStream_t st)
+                             const hydro_params *prm, int32_t *err32, hipStream_t st)
 {
+    int *err_dev = (int *)err32;
     const double gamma = prm->gamma;
     auto set = [&](int stage) {
         if (L.nb) L.pre = pre[stage];
@@ -677,23 +690,26 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
     }
     prof(PG_TRACE, 1, st);
     prof(PG_FLUX1, 0, st);
-    for (int d = 0; d < 3; ++d)
-        hipLaunchKernelGGL(k_flux1, set(ST_F1 + d), blk, 0, st, L, d, gamma);
+    hipLaunchKernelGGL(k_flux1<0>, set(ST_F1 + 0), blk, 0, st, L, gamma);
+    hipLaunchKernelGGL(k_flux1<1>, set(ST_F1 + 1), blk, 0, st, L, gamma);
+    hipLaunchKernelGGL(k_flux1<2>, set(ST_F1 + 2), blk, 0, st, L, gamma);
     prof(PG_FLUX1, 1, st);
     prof(PG_FLUX2, 0, st);
-    for (int t = 0; t < 3; ++t)
-        for (int sd = 0; sd < 3; ++sd)
-            if (sd != t)
-                hipLaunchKernelGGL(k_flux2, set(ST_F2 + FAM(t, sd)), blk, 0, st, L, t, sd,
-                                   gamma, (int *)err_dev);
+    hipLaunchKernelGGL((k_flux2<0, 1>), set(ST_F2 + FAM(0, 1)), blk, 0, st, L, gamma, err_dev);
+    hipLaunchKernelGGL((k_flux2<0, 2>), set(ST_F2 + FAM(0, 2)), blk, 0, st, L, gamma, err_dev);
+    hipLaunchKernelGGL((k_flux2<1, 0>), set(ST_F2 + FAM(1, 0)), blk, 0, st, L, gamma, err_dev);
+    hipLaunchKernelGGL((k_flux2<1, 2>), set(ST_F2 + FAM(1, 2)), blk, 0, st, L, gamma, err_dev);
+    hipLaunchKernelGGL((k_flux2<2, 0>), set(ST_F2 + FAM(2, 0)), blk, 0, st, L, gamma, err_dev);
+    hipLaunchKernelGGL((k_flux2<2, 1>), set(ST_F2 + FAM(2, 1)), blk, 0, st, L, gamma, err_dev);
     prof(PG_FLUX2, 1, st);
     prof(PG_FLUX3, 0, st);
-    for (int d = 0; d < 3; ++d)
-        hipLaunchKernelGGL(k_flux3, set(ST_F3 + d), blk, 0, st, L, d, gamma, (int *)err_dev);
+    hipLaunchKernelGGL(k_flux3<0>, set(ST_F3 + 0), blk, 0, st, L, gamma, err_dev);
+    hipLaunchKernelGGL(k_flux3<1>, set(ST_F3 + 1), blk, 0, st, L, gamma, err_dev);
+    hipLaunchKernelGGL(k_flux3<2>, set(ST_F3 + 2), blk, 0, st, L, gamma, err_dev);
     prof(PG_FLUX3, 1, st);
     prof(PG_UPDATE, 0, st);
     hipLaunchKernelGGL(k_update, set(ST_UPD), blk, 0, st, L, gamma, prm->grav[0],
-                       prm->grav[1], prm->grav[2], (int *)err_dev);
+                       prm->grav[1], prm->grav[2], err_dev);
     prof(PG_UPDATE, 1, st);
     return launch_status();
 }

@@ -1,0 +1,230 @@
+"""Continuous-batching server for independent hydro runs on one GPU.
+
+Each request is a whole hydro run: a cubic box, an initial-condition family
+and seed, and a number of steps.  The server admits arriving requests while
+the HBM ledger (state ping-pong buffers plus the request's share of the
+batch workspace) stays within the budget and a slot is free, keeps every
+admitted state resident on the device, and advances all active requests
+together: one batched ghost-fill + timestep launch pair and one batched
+advance per iteration (advance_boxes, each box with its own timestep, so a
+request's result does not depend on what it is batched with).  Requests that
+arrive while others run join at the next iteration; finished ones leave
+immediately and their memory returns to the ledger.
+
+The paper's codes keep all simulation data on the GPU and copy to the host
+only for checkpoints (Sec. III), reuse device memory through a caching pool
+allocator (Sec. III), and find that small boxes need many-at-once execution
+to fill a GPU (Sec. IV-A); this loop applies the three to a stream of runs.
+
+The scheduler is written against a small executor interface so the
+admission and retirement logic can be exercised without a GPU; the only
+product executor is GpuExecutor, which calls the HIP library.
+"""
+import collections
+import math
+import time
+
+
+class Request:
+    __slots__ = ("id", "arrival", "n", "steps", "family", "seed", "remaining", "need",
+                 "t_admit", "t_done", "done_token", "handle", "result", "cells")
+
+    def __init__(self, spec):
+        self.id = spec["id"]
+        self.arrival = float(spec["arrival"])
+        self.n = int(spec["n"])
+        self.steps = int(spec["steps"])
+        self.family = spec["family"]
+        self.seed = spec["seed"]
+        self.remaining = self.steps
+        self.cells = self.n ** 3
+        self.need = 0
+        self.t_admit = None
+        self.t_done = None
+        self.done_token = None
+        self.handle = None
+        self.result = None
+
+
+class GpuExecutor:
+    """Device side of the server: states in device memory, one batched plan per
+    membership of the active set, every launch on one stream."""
+
+    def __init__(self, device="cuda", keep_results=False, capture_graphs=False):
+        import torch
+        from . import hydro, inputs
+        self.torch = torch
+        self.hydro = hydro
+        self.inputs = inputs
+        self.device = device
+        self.keep_results = keep_results
+        hydro.lib()
+        self.stream = torch.cuda.current_stream()
+        self.active = []
+        self.plan = None
+        self.prm = None
+        self.err = torch.zeros(1, dtype=torch.int32, device=device)
+
+    # -- memory ledger
+    def bytes_needed(self, req):
+        box = self.inputs.box_desc((req.n,) * 3)
+        return 2 * 8 * self.hydro.state_elems(box) + self.hydro.workspace_bytes(box)
+
+    # -- membership
+    def admit(self, req):
+        torch = self.torch
+        U, box, prm = self.inputs.request_state({"family": req.family, "n": req.n,
+                                                 "seed": req.seed})
+        if self.prm is None:
+            self.prm = prm
+        Ud = torch.as_tensor(U).to(self.device, non_blocking=False)
+        req.handle = {"U": Ud, "Un": torch.empty_like(Ud), "box": box}
+
+    def release(self, req):
+        if self.keep_results:
+            req.result = req.handle["U"].cpu().numpy()
+        req.handle = None
+
+    def set_batch(self, reqs):
+        torch = self.torch
+        self.active = list(reqs)
+        if self.plan is not None:
+            self.plan.close()
+            self.plan = None
+        if not reqs:
+            return
+        boxes = [r.handle["box"] for r in reqs]
+        self.plan = self.hydro.Plan(boxes)
+        self.ws = torch.empty(max(self.plan.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.dt = torch.zeros(len(reqs), dtype=torch.float64, device=self.device)
+        self._pointers()
+
+    def _pointers(self):
+        self.pa = self.hydro.pointer_array([r.handle["U"] for r in self.active], self.device)
+        self.pb = self.hydro.pointer_array([r.handle["Un"] for r in self.active], self.device)
+
+    # -- one iteration: every active request advances one step with its own dt
+    def step(self):
+        h = self.hydro
+        h.estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, None)
+        h.advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt, self.ws, self.err,
+                        dt_stride=1)
+        for r in self.active:
+            r.handle["U"], r.handle["Un"] = r.handle["Un"], r.handle["U"]
+        self.pa, self.pb = self.pb, self.pa
+
+    def mark(self):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record()
+        return ev
+
+    def wait(self, token):
+        token.synchronize()
+
+    def elapsed(self, t0_token, token):
+        return t0_token.elapsed_time(token) * 1e-3
+
+    def error_bits(self):
+        return int(self.err.item())
+
+
+class Server:
+    """Admission, batching and retirement.  ``clock`` returns seconds; the
+    executor supplies device timing tokens (events), so latency is measured
+    on the device timeline: completion = end of the request's last step."""
+
+    def __init__(self, executor, budget_bytes=200e9, max_active=64, max_ahead=2,
+                 clock=time.perf_counter, sleep=time.sleep):
+        self.ex = executor
+        self.budget = float(budget_bytes)
+        self.max_active = int(max_active)
+        self.max_ahead = int(max_ahead)
+        self.clock = clock
+        self.sleep = sleep
+        self.ledger = 0.0
+        self.peak_ledger = 0.0
+        self.iterations = 0
+        self.peak_active = 0
+
+    def run(self, specs):
+        reqs = [Request(s) for s in specs]
+        for r in reqs:
+            r.need = self.ex.bytes_needed(r)
+            if r.need > self.budget:
+                raise ValueError("request %d needs %.3g B, more than the %.3g B budget"
+                                 % (r.id, r.need, self.budget))
+        pending = collections.deque(sorted(reqs, key=lambda r: (r.arrival, r.id)))
+        active = []
+        inflight = collections.deque()
+        done = []
+        t0 = self.clock()
+        t0_tok = self.ex.mark()
+        changed = False
+        while pending or active:
+            now = self.clock() - t0
+            # admission: FIFO, while a slot and the budget allow
+            while (pending and pending[0].arrival <= now and len(active) < self.max_active
+                   and self.ledger + pending[0].need <= self.budget):
+                r = pending.popleft()
+                self.ex.admit(r)
+                r.t_admit = now
+                self.ledger += r.need
+                active.append(r)
+                changed = True
+            self.peak_ledger = max(self.peak_ledger, self.ledger)
+            if not active:
+                # idle until the next arrival
+                wait = pending[0].arrival - (self.clock() - t0)
+                if wait > 0:
+                    self.sleep(wait)
+                continue
+            if changed:
+                self.ex.set_batch(active)
+                changed = False
+            self.peak_active = max(self.peak_active, len(active))
+            self.ex.step()
+            self.iterations += 1
+            for r in active:
+                r.remaining -= 1
+            fin = [r for r in active if r.remaining == 0]
+            tok = self.ex.mark()
+            inflight.append(tok)
+            if fin:
+                for r in fin:
+                    r.done_token = tok
+                    self.ex.release(r)
+                    self.ledger -= r.need
+                    done.append(r)
+                active = [r for r in active if r.remaining > 0]
+                changed = True
+            # bound how far the host runs ahead of the device
+            while len(inflight) > self.max_ahead:
+                self.ex.wait(inflight.popleft())
+        while inflight:
+            self.ex.wait(inflight.popleft())
+        for r in done:
+            r.t_done = self.ex.elapsed(t0_tok, r.done_token)
+        self.requests = sorted(done, key=lambda r: r.id)
+        return self.requests
+
+    def metrics(self, skip=0):
+        """Latency percentiles and throughput over the requests after the first
+        ``skip`` (by id, the warm-up)."""
+        rs = [r for r in self.requests if r.id >= skip]
+        lat = sorted(r.t_done - r.arrival for r in rs)
+        cu = sum(r.cells * r.steps for r in rs)
+        t_first = min(r.arrival for r in rs)
+        t_last = max(r.t_done for r in rs)
+        span = max(t_last - t_first, 1e-12)
+
+        def pct(q):
+            if not lat:
+                return None
+            k = min(len(lat) - 1, max(0, int(math.ceil(q * len(lat))) - 1))
+            return lat[k]
+
+        return {"requests": len(rs), "p50_s": pct(0.50), "p99_s": pct(0.99),
+                "mean_s": sum(lat) / len(lat) if lat else None,
+                "cell_updates": cu, "span_s": span, "cu_per_s": cu / span,
+                "iterations": self.iterations, "peak_active": self.peak_active,
+                "peak_ledger_bytes": self.peak_ledger}
