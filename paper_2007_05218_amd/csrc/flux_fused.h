@@ -1,0 +1,376 @@
+// flux_fused.h -- the second half of the CTU step in one kernel:
+// corner coupling + round-2 HLLC, final states + round-3 HLLC, conservative
+// update, for one box tile, marching along z.
+//
+// Inputs (HBM workspace, written by the trace and round-1 kernels): the
+// traced face states of every cell in all three directions and the round-1
+// fluxes.  Output: the new state of the tile's cells.  Nothing else goes
+// back to HBM: in-plane neighbour exchanges go through LDS, and the
+// z-direction couplings (fluxes through z-faces and the z-differences of
+// the (z|s) fluxes) are carried from plane to plane in registers.
+//
+// Tile: a 256-thread block covers BX x BY columns (BX*BY = 256) of which the
+// inner (BX-2) x (BY-2) are output columns; the one-column ring supplies the
+// transverse neighbours every flux difference needs.  A block marches over
+// planes z0-1 .. z1 of its z-segment [z0, z1); iteration q computes the
+// in-plane round-2 fluxes of plane q, the z-face fluxes between q-1 and q,
+// and finishes plane q-1 (its final x/y states need the (z|s) fluxes on both
+// of its z-faces).
+//
+// Error bits: a transverse-corrected state raises the fallback bit only
+// where the whole-box step computes it (the flux it feeds lies in that
+// flux's region of the box) and where this tile computes it from valid data;
+// overlapping tiles may raise the same bit twice, which OR absorbs.
+#pragma once
+
+namespace {
+
+constexpr int kFT = 256;  // threads of a fused-flux block
+
+struct XBuf {
+    double v[10][kFT];
+};
+
+__device__ __forceinline__ void put5(double (*b)[kFT], int k0, int t, double a0, double a1,
+                                     double a2, double a3, double a4)
+{
+    b[k0 + 0][t] = a0;
+    b[k0 + 1][t] = a1;
+    b[k0 + 2][t] = a2;
+    b[k0 + 3][t] = a3;
+    b[k0 + 4][t] = a4;
+}
+__device__ __forceinline__ void putF(double (*b)[kFT], int k0, int t, const Face &f)
+{
+    put5(b, k0, t, f.r, f.u, f.v, f.w, f.p);
+}
+__device__ __forceinline__ void putX(double (*b)[kFT], int k0, int t, const Flux &f)
+{
+    put5(b, k0, t, f.m, f.mu, f.mv, f.mw, f.e);
+}
+__device__ __forceinline__ Face getF(double (*b)[kFT], int k0, int t)
+{
+    Face f;
+    f.r = b[k0 + 0][t];
+    f.u = b[k0 + 1][t];
+    f.v = b[k0 + 2][t];
+    f.w = b[k0 + 3][t];
+    f.p = b[k0 + 4][t];
+    return f;
+}
+__device__ __forceinline__ Flux getX(double (*b)[kFT], int k0, int t)
+{
+    Flux f;
+    f.m = b[k0 + 0][t];
+    f.mu = b[k0 + 1][t];
+    f.mv = b[k0 + 2][t];
+    f.mw = b[k0 + 3][t];
+    f.e = b[k0 + 4][t];
+    return f;
+}
+
+// hi - lo, component-wise
+__device__ __forceinline__ Flux fdiff(const Flux &hi, const Flux &lo)
+{
+    Flux d;
+    d.m = hi.m - lo.m;
+    d.mu = hi.mu - lo.mu;
+    d.mv = hi.mv - lo.mv;
+    d.mw = hi.mw - lo.mw;
+    d.e = hi.e - lo.e;
+    return d;
+}
+
+__device__ __forceinline__ Flux load_flux(const WS &ws, int base, long long o)
+{
+    Flux f;
+    f.m = ws.f(base + 0)[o];
+    f.mu = ws.f(base + 1)[o];
+    f.mv = ws.f(base + 2)[o];
+    f.mw = ws.f(base + 3)[o];
+    f.e = ws.f(base + 4)[o];
+    return f;
+}
+
+// corner state: prim(U(q) - fac * dF), with the rejection rule
+__device__ __forceinline__ Face corner_state(const Face &q, const Flux &dF, double fac,
+                                             double gm1, int &fb)
+{
+    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
+    double V0 = q.r - fac * dF.m;
+    double V1 = (q.r * q.u) - fac * dF.mu;
+    double V2 = (q.r * q.v) - fac * dF.mv;
+    double V3 = (q.r * q.w) - fac * dF.mw;
+    double V4 = E - fac * dF.e;
+    fb = 0;
+    return accept(q, V0, V1, V2, V3, V4, gm1, fb);
+}
+
+// final state: prim((U(q) - f1 * dA) - f2 * dB), with the rejection rule
+__device__ __forceinline__ Face final_state2(const Face &q, const Flux &dA, const Flux &dB,
+                                             double f1, double f2, double gm1, int &fb)
+{
+    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
+    double V0 = (q.r - f1 * dA.m) - f2 * dB.m;
+    double V1 = ((q.r * q.u) - f1 * dA.mu) - f2 * dB.mu;
+    double V2 = ((q.r * q.v) - f1 * dA.mv) - f2 * dB.mv;
+    double V3 = ((q.r * q.w) - f1 * dA.mw) - f2 * dB.mw;
+    double V4 = (E - f1 * dA.e) - f2 * dB.e;
+    fb = 0;
+    return accept(q, V0, V1, V2, V3, V4, gm1, fb);
+}
+
+__device__ __forceinline__ bool inr(int v, int lo, int hi) { return v >= lo && v <= hi; }
+
+// tile decomposition of one box for the fused kernels
+struct Tile {
+    int BX, BY, TX, TY;
+    int x0, y0, z0, z1;
+};
+
+__device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long nblk)
+{
+    Tile T;
+    T.BX = g.tbx;
+    T.BY = kFT / g.tbx;
+    T.TX = T.BX - 2;
+    T.TY = T.BY - 2;
+    const int ntx = (g.n[0] + T.TX - 1) / T.TX;
+    const int nty = (g.n[1] + T.TY - 1) / T.TY;
+    // spread neighbouring tiles over one XCD: blocks are dealt round-robin to
+    // the 8 XCDs, so give each XCD a contiguous run of tiles (shared halo
+    // rows then meet in that XCD's L2)
+    long long per = nblk / 8, rem = nblk % 8;
+    long long x = blk % 8, i = blk / 8;
+    long long t = x * per + (x < rem ? x : rem) + i;
+    if (t >= nblk) t = blk;  // (cannot happen; keeps the mapping total)
+    const int ix = (int)(t % ntx);
+    t /= ntx;
+    const int iy = (int)(t % nty);
+    const int iz = (int)(t / nty);
+    T.x0 = ix * T.TX;
+    T.y0 = iy * T.TY;
+    T.z0 = iz * g.tzs;
+    T.z1 = min(g.n[2], T.z0 + g.tzs);
+    return T;
+}
+
+__host__ inline long long fused_blocks(const Geo &g)
+{
+    const int TX = g.tbx - 2, TY = kFT / g.tbx - 2;
+    long long ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
+    long long nzs = (g.n[2] + g.tzs - 1) / g.tzs;
+    return ntx * nty * nzs;
+}
+
+#ifndef HYDRO_FUSED_WAVES
+#define HYDRO_FUSED_WAVES 2
+#endif
+__global__ void __launch_bounds__(kFT) __attribute__((amdgpu_waves_per_eu(HYDRO_FUSED_WAVES)))
+k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_dev)
+{
+    __shared__ XBuf xa, xb;
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    const WS &ws = o.ws;
+    const Tile T = tile_of(g, o.blk, o.nblk);
+    const int t = threadIdx.x;
+    const int tx = t % T.BX, ty = t / T.BX;
+    const int x = T.x0 - 1 + tx, y = T.y0 - 1 + ty;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    // loads come from the clamped column (inside the traced region); results
+    // of columns outside it are never used
+    const int xc = min(x, n0), yc = min(y, n1);
+    const int tL = tx >= 1 ? t - 1 : t, tR = tx + 1 < T.BX ? t + 1 : t;
+    const int tD = ty >= 1 ? t - T.BX : t, tU = ty + 1 < T.BY ? t + T.BX : t;
+    const bool hasL = tx >= 1, hasR = tx + 1 < T.BX, hasD = ty >= 1, hasU = ty + 1 < T.BY;
+    const bool outc = tx >= 1 && tx <= T.TX && ty >= 1 && ty <= T.TY && x < n0 && y < n1;
+
+    const double gm1 = gamma - 1.0;
+    const double dt = *o.dt;
+    const double fx3 = dt / (3.0 * g.dx[0]), fy3 = dt / (3.0 * g.dx[1]),
+                 fz3 = dt / (3.0 * g.dx[2]);
+    const double fx2 = dt / (2.0 * g.dx[0]), fy2 = dt / (2.0 * g.dx[1]),
+                 fz2 = dt / (2.0 * g.dx[2]);
+    const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
+    const long long sx = 1, sy = g.s[0], sz = (long long)g.s[0] * g.s[1];
+
+    // plane-to-plane carries (values of the previous plane)
+    // (zero until the first plane has been processed; the values derived from
+    // them in the first two planes of a segment are never used)
+    Face c_zx_hi = {}, c_zy_hi = {}, fz_hi = {};  // corner (z|x), (z|y), final z: high face
+    Flux F2zx = {}, F2zy = {};    // (z|x), (z|y) fluxes through the plane's low z-face
+    Flux dF2xz = {}, dF2yz = {};  // x-difference of (x|z), y-difference of (y|z) fluxes
+    Flux F3z = {};                // round-3 flux through the plane's low z-face
+    int err = 0;
+
+    for (int q = T.z0 - 1; q <= T.z1; ++q) {
+        const long long oc = cell(g, xc, yc, q);
+        // ---------------------------------------------------- loads
+        const Face qx_lo = load_face(ws, QLO(0, 0), oc), qx_hi = load_face(ws, QHI(0, 0), oc);
+        const Face qy_lo = load_face(ws, QLO(1, 0), oc), qy_hi = load_face(ws, QHI(1, 0), oc);
+        const Face qz_lo = load_face(ws, QLO(2, 0), oc), qz_hi = load_face(ws, QHI(2, 0), oc);
+        const Flux dF1x = fdiff(load_flux(ws, F1F(0, 0), oc + sx), load_flux(ws, F1F(0, 0), oc));
+        const Flux dF1y = fdiff(load_flux(ws, F1F(1, 0), oc + sy), load_flux(ws, F1F(1, 0), oc));
+        const Flux dF1z = fdiff(load_flux(ws, F1F(2, 0), oc + sz), load_flux(ws, F1F(2, 0), oc));
+
+        // ---------------------------------------------------- A: high corner states
+        int fb;
+        {
+            Face h = corner_state(qx_hi, dF1y, fy3, gm1, fb);  // (x|y)
+            if (fb && hasR && inr(x + 1, 0, n0) && inr(y, 0, n1 - 1) && inr(q, -1, n2)) err |= fb;
+            putF(xa.v, 0, t, h);
+            h = corner_state(qy_hi, dF1x, fx3, gm1, fb);  // (y|x)
+            if (fb && hasU && inr(y + 1, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
+            putF(xa.v, 5, t, h);
+            h = corner_state(qx_hi, dF1z, fz3, gm1, fb);  // (x|z)
+            if (fb && hasR && inr(x + 1, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
+            putF(xb.v, 0, t, h);
+            h = corner_state(qy_hi, dF1z, fz3, gm1, fb);  // (y|z)
+            if (fb && hasU && inr(y + 1, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
+            putF(xb.v, 5, t, h);
+        }
+        __syncthreads();
+        // ---------------------------------------------------- B: round-2 fluxes
+        Flux F2xy, F2yx, F2xz, F2yz;
+        {
+            Face l = corner_state(qx_lo, dF1y, fy3, gm1, fb);
+            if (fb && hasL && inr(x, 0, n0) && inr(y, 0, n1 - 1) && inr(q, -1, n2)) err |= fb;
+            F2xy = hllc(getF(xa.v, 0, tL), l, 0, gamma, gm1);
+            l = corner_state(qy_lo, dF1x, fx3, gm1, fb);
+            if (fb && hasD && inr(y, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
+            F2yx = hllc(getF(xa.v, 5, tD), l, 1, gamma, gm1);
+            l = corner_state(qx_lo, dF1z, fz3, gm1, fb);
+            if (fb && hasL && inr(x, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
+            F2xz = hllc(getF(xb.v, 0, tL), l, 0, gamma, gm1);
+            l = corner_state(qy_lo, dF1z, fz3, gm1, fb);
+            if (fb && hasD && inr(y, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
+            F2yz = hllc(getF(xb.v, 5, tD), l, 1, gamma, gm1);
+        }
+        // z-families: the flux through the z-face between q-1 and q
+        {
+            const bool valid = q >= T.z0;  // the plane below was computed here
+            Face l = corner_state(qz_lo, dF1x, fx3, gm1, fb);  // (z|x)
+            if (fb && valid && inr(q, 0, n2) && inr(x, 0, n0 - 1) && inr(y, -1, n1)) err |= fb;
+            Flux Fzx = hllc(c_zx_hi, l, 2, gamma, gm1);
+            Face h = corner_state(qz_hi, dF1x, fx3, gm1, fb);
+            if (fb && q + 1 <= T.z1 && inr(q + 1, 0, n2) && inr(x, 0, n0 - 1) && inr(y, -1, n1))
+                err |= fb;
+            c_zx_hi = h;
+            l = corner_state(qz_lo, dF1y, fy3, gm1, fb);  // (z|y)
+            if (fb && valid && inr(q, 0, n2) && inr(y, 0, n1 - 1) && inr(x, -1, n0)) err |= fb;
+            Flux Fzy = hllc(c_zy_hi, l, 2, gamma, gm1);
+            h = corner_state(qz_hi, dF1y, fy3, gm1, fb);
+            if (fb && q + 1 <= T.z1 && inr(q + 1, 0, n2) && inr(y, 0, n1 - 1) && inr(x, -1, n0))
+                err |= fb;
+            c_zy_hi = h;
+            // z-differences of the (z|s) fluxes of plane q-1
+            const Flux dzx = fdiff(Fzx, F2zx), dzy = fdiff(Fzy, F2zy);
+            F2zx = Fzx;
+            F2zy = Fzy;
+            __syncthreads();
+            // ------------------------------------------------ C: publish round-2 fluxes
+            putX(xa.v, 0, t, F2xy);
+            putX(xa.v, 5, t, F2yx);
+            putX(xb.v, 0, t, F2xz);
+            putX(xb.v, 5, t, F2yz);
+            __syncthreads();
+            // ------------------------------------------------ D: final states
+            // final z state of plane q
+            const Flux dxy = fdiff(getX(xa.v, 0, tR), F2xy);
+            const Flux dyx = fdiff(getX(xa.v, 5, tU), F2yx);
+            const bool zin = hasL && hasR && hasD && hasU && x < n0 && y < n1;
+            Face zl = final_state2(qz_lo, dxy, dyx, fx2, fy2, gm1, fb);
+            if (fb && zin && inr(q, 0, n2) && q >= T.z0 && x >= 0 && y >= 0) err |= fb;
+            Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, fb);
+            if (fb && zin && inr(q + 1, 0, n2) && q + 1 <= T.z1 && x >= 0 && y >= 0) err |= fb;
+            Flux F3zq = hllc(fz_hi, zl, 2, gamma, gm1);
+            fz_hi = zh;
+            // differences of the in-plane (s|z) fluxes of plane q (used next plane)
+            const Flux dxz = fdiff(getX(xb.v, 0, tR), F2xz);
+            const Flux dyz = fdiff(getX(xb.v, 5, tU), F2yz);
+            // final x and y states of plane q-1
+            const int p = q - 1;
+            const bool pv = p >= T.z0;  // plane p is finished in this segment
+            const long long op = oc - sz;
+            Face xl, xh, yl, yh;
+            {
+                const Face a = load_face(ws, QLO(0, 0), op), b = load_face(ws, QHI(0, 0), op);
+                xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, fb);
+                if (fb && pv && hasL && hasD && hasU && inr(x, 0, n0) && inr(y, 0, n1 - 1) &&
+                    inr(p, 0, n2 - 1))
+                    err |= fb;
+                xh = final_state2(b, dF2yz, dzy, fy2, fz2, gm1, fb);
+                if (fb && pv && hasR && hasD && hasU && inr(x + 1, 0, n0) && inr(y, 0, n1 - 1) &&
+                    inr(p, 0, n2 - 1))
+                    err |= fb;
+            }
+            {
+                const Face a = load_face(ws, QLO(1, 0), op), b = load_face(ws, QHI(1, 0), op);
+                yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, fb);
+                if (fb && pv && hasD && hasL && hasR && inr(y, 0, n1) && inr(x, 0, n0 - 1) &&
+                    inr(p, 0, n2 - 1))
+                    err |= fb;
+                yh = final_state2(b, dF2xz, dzx, fx2, fz2, gm1, fb);
+                if (fb && pv && hasU && hasL && hasR && inr(y + 1, 0, n1) && inr(x, 0, n0 - 1) &&
+                    inr(p, 0, n2 - 1))
+                    err |= fb;
+            }
+            dF2xz = dxz;
+            dF2yz = dyz;
+            __syncthreads();
+            // ------------------------------------------------ E/F: round-3 in-plane fluxes
+            putF(xa.v, 0, t, xh);
+            putF(xa.v, 5, t, yh);
+            __syncthreads();
+            const Flux F3x = hllc(getF(xa.v, 0, tL), xl, 0, gamma, gm1);
+            const Flux F3y = hllc(getF(xa.v, 5, tD), yl, 1, gamma, gm1);
+            putX(xb.v, 0, t, F3x);
+            putX(xb.v, 5, t, F3y);
+            __syncthreads();
+            // ------------------------------------------------ H: update plane p
+            if (outc && pv) {
+                const Flux Hx = getX(xb.v, 0, tR), Hy = getX(xb.v, 5, tU);
+                const double Fx[5][2] = {{F3x.m, Hx.m}, {F3x.mu, Hx.mu}, {F3x.mv, Hx.mv},
+                                         {F3x.mw, Hx.mw}, {F3x.e, Hx.e}};
+                const double Fy[5][2] = {{F3y.m, Hy.m}, {F3y.mu, Hy.mu}, {F3y.mv, Hy.mv},
+                                         {F3y.mw, Hy.mw}, {F3y.e, Hy.e}};
+                const double Fz[5][2] = {{F3z.m, F3zq.m}, {F3z.mu, F3zq.mu}, {F3z.mv, F3zq.mv},
+                                         {F3z.mw, F3zq.mw}, {F3z.e, F3zq.e}};
+                const long long c0 = cell(g, x, y, p);
+                double Uo[5], Us[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    double du = ax * (Fx[v][1] - Fx[v][0]);
+                    du = du + ay * (Fy[v][1] - Fy[v][0]);
+                    du = du + az * (Fz[v][1] - Fz[v][0]);
+                    Uo[v] = o.U[v * g.cs + c0];
+                    Us[v] = Uo[v] - du;
+                }
+                const double h = 0.5 * dt;
+                const double gg[3] = {gx, gy, gz};
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if (gg[e] != 0.0) {
+                        double hg = h * gg[e];
+                        double mnew = Us[1 + e] + hg * (Uo[0] + Us[0]);
+                        Us[4] = Us[4] + hg * (Uo[1 + e] + mnew);
+                        Us[1 + e] = mnew;
+                    }
+                Prim qn = prim_of(Us[0], Us[1], Us[2], Us[3], Us[4], gm1);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    if (!isfinite(Us[v])) err |= HYDRO_ERR_NONFINITE;
+                    o.Un[v * g.cs + c0] = Us[v];
+                }
+                if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
+                if (qn.p <= 0.0) err |= HYDRO_ERR_P;
+            }
+            F3z = F3zq;
+            __syncthreads();
+        }
+    }
+    if (err) atomicOr(err_dev, err);
+}
+
+}  // namespace

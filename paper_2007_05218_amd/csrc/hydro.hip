@@ -49,6 +49,8 @@ struct Geo {
     long long cs;  // doubles per component (s0*s1*s2)
     double dx[3];
     int bc_lo[3], bc_hi[3];
+    int tbx;  // fused kernels: tile width in columns (block = 256 threads = tbx x 256/tbx)
+    int tzs;  // fused kernels: z-segment length per block
 };
 
 // workspace fields
@@ -62,10 +64,7 @@ __host__ __device__ constexpr int F3F(int d, int v) { return 81 + d * 5 + v; }
 constexpr int kFields = 96;
 
 // stages (block-count prefix arrays are kept per stage)
-enum {
-    ST_FILL = 0, ST_DT = 1, ST_PRIM = 2, ST_TRACE = 3, ST_F1 = 4, ST_F2 = 7, ST_F3 = 13,
-    ST_UPD = 16, ST_COUNT = 17
-};
+enum { ST_FILL = 0, ST_DT = 1, ST_PRIM = 2, ST_TRACE = 3, ST_F1 = 4, ST_FUSED = 7, ST_COUNT = 8 };
 constexpr int kDtCellsPerThread = 4;
 constexpr long long kDtMaxBlocks = 4096;
 
@@ -109,16 +108,6 @@ __host__ __device__ inline Reg stage_reg(const Geo &g, int st)
         int d = st - ST_F1;
         for (int e = 0; e < 3; ++e) { lo[e] = -1; hi[e] = n[e] + 1; }
         lo[d] = 0;
-    } else if (st >= ST_F2 && st < ST_F2 + 6) {
-        int fam = st - ST_F2;
-        int t = fam / 2, r2 = fam % 2;
-        int sd = r2 < t ? r2 : r2 + 1;
-        int d = 3 - t - sd;
-        lo[t] = 0; hi[t] = n[t] + 1;
-        lo[sd] = 0; hi[sd] = n[sd];
-        lo[d] = -1; hi[d] = n[d] + 1;
-    } else if (st >= ST_F3 && st < ST_F3 + 3) {
-        hi[st - ST_F3] = n[st - ST_F3] + 1;
     }
     for (int e = 0; e < 3; ++e) {
         r.lo[e] = lo[e];
@@ -153,6 +142,11 @@ __host__ inline long long stage_items(const Geo &g, int st)
 
 __host__ inline long long stage_blocks(const Geo &g, int st)
 {
+    if (st == ST_FUSED) {  // tiles of (tbx-2) x (256/tbx-2) columns by z-segments of tzs
+        const long long TX = g.tbx - 2, TY = 256 / g.tbx - 2;
+        return ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) *
+               ((g.n[2] + g.tzs - 1) / g.tzs);
+    }
     long long items = stage_items(g, st);
     if (st == ST_DT) {
         long long b = (items + (long long)kBlock * kDtCellsPerThread - 1) /
@@ -462,130 +456,7 @@ __global__ void __launch_bounds__(kBlock) k_flux1(Launch L, double gamma)
     store_flux(o.ws, F1F(d, 0), c0, hllc(Lf, Rf, d, gamma, gamma - 1.0));
 }
 
-// ---------------------------------------------------------------- flux2
-
-__device__ __forceinline__ Face corner(const WS &ws, const Face &q, int sd, long long oc,
-                                       long long ss, double fac, double gm1, int &err)
-{
-    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
-    const double *F0 = ws.f(F1F(sd, 0)), *F1 = ws.f(F1F(sd, 1)), *F2 = ws.f(F1F(sd, 2)),
-                 *F3 = ws.f(F1F(sd, 3)), *F4 = ws.f(F1F(sd, 4));
-    const long long oh = oc + ss;
-    double V0 = q.r - fac * (F0[oh] - F0[oc]);
-    double V1 = (q.r * q.u) - fac * (F1[oh] - F1[oc]);
-    double V2 = (q.r * q.v) - fac * (F2[oh] - F2[oc]);
-    double V3 = (q.r * q.w) - fac * (F3[oh] - F3[oc]);
-    double V4 = E - fac * (F4[oh] - F4[oc]);
-    return accept(q, V0, V1, V2, V3, V4, gm1, err);
-}
-
-template <int t, int sd>
-__global__ void __launch_bounds__(kBlock) k_flux2(Launch L, double gamma, int *err_dev)
-{
-    Box1 o = resolve(L);
-    const Geo &g = o.g;
-    int i, j, k;
-    if (!reg_cell(stage_reg(g, ST_F2 + FAM(t, sd)), o.blk * kBlock + threadIdx.x, i, j, k))
-        return;
-    const double gm1 = gamma - 1.0;
-    const double fac = *o.dt / (3.0 * g.dx[sd]);
-    const long long c0 = cell(g, i, j, k);
-    const long long cl = c0 - stride(g, t);
-    const long long ss = stride(g, sd);
-    int err = 0;
-    Face qL = corner(o.ws, load_face(o.ws, QHI(t, 0), cl), sd, cl, ss, fac, gm1, err);
-    Face qR = corner(o.ws, load_face(o.ws, QLO(t, 0), c0), sd, c0, ss, fac, gm1, err);
-    store_flux(o.ws, F2F(FAM(t, sd), 0), c0, hllc(qL, qR, t, gamma, gm1));
-    if (err) atomicOr(err_dev, err);
-}
-
-// ---------------------------------------------------------------- flux3
-
-__device__ __forceinline__ Face final_state(const WS &ws, const Face &q, int fa, int fb,
-                                            long long oc, long long sa, long long sb,
-                                            double f1, double f2, double gm1, int &err)
-{
-    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
-    double U[5] = {q.r, q.r * q.u, q.r * q.v, q.r * q.w, E};
-    double V[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        const double *A = ws.f(F2F(fa, v)), *B = ws.f(F2F(fb, v));
-        V[v] = (U[v] - f1 * (A[oc + sa] - A[oc])) - f2 * (B[oc + sb] - B[oc]);
-    }
-    return accept(q, V[0], V[1], V[2], V[3], V[4], gm1, err);
-}
-
-template <int d>
-__global__ void __launch_bounds__(kBlock) k_flux3(Launch L, double gamma, int *err_dev)
-{
-    Box1 o = resolve(L);
-    const Geo &g = o.g;
-    int i, j, k;
-    if (!reg_cell(stage_reg(g, ST_F3 + d), o.blk * kBlock + threadIdx.x, i, j, k)) return;
-    const double gm1 = gamma - 1.0;
-    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    const double dt = *o.dt;
-    const double f1 = dt / (2.0 * g.dx[t1]);
-    const double f2 = dt / (2.0 * g.dx[t2]);
-    const long long c0 = cell(g, i, j, k);
-    const long long cl = c0 - stride(g, d);
-    const long long s1 = stride(g, t1), s2 = stride(g, t2);
-    const int fa = FAM(t1, t2), fb = FAM(t2, t1);
-    int err = 0;
-    Face qL = final_state(o.ws, load_face(o.ws, QHI(d, 0), cl), fa, fb, cl, s1, s2, f1, f2,
-                          gm1, err);
-    Face qR = final_state(o.ws, load_face(o.ws, QLO(d, 0), c0), fa, fb, c0, s1, s2, f1, f2,
-                          gm1, err);
-    store_flux(o.ws, F3F(d, 0), c0, hllc(qL, qR, d, gamma, gm1));
-    if (err) atomicOr(err_dev, err);
-}
-
-// ---------------------------------------------------------------- update
-
-__global__ void __launch_bounds__(kBlock) k_update(Launch L, double gamma, double gx,
-                                                   double gy, double gz, int *err_dev)
-{
-    Box1 o = resolve(L);
-    const Geo &g = o.g;
-    int i, j, k;
-    if (!reg_cell(stage_reg(g, ST_UPD), o.blk * kBlock + threadIdx.x, i, j, k)) return;
-    const double gm1 = gamma - 1.0;
-    const double dt = *o.dt;
-    const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
-    const long long c0 = cell(g, i, j, k);
-    const long long sy = g.s[0], sz = (long long)g.s[0] * g.s[1];
-    double Uo[5], Us[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        const double *X = o.ws.f(F3F(0, v)), *Y = o.ws.f(F3F(1, v)), *Z = o.ws.f(F3F(2, v));
-        double du = ax * (X[c0 + 1] - X[c0]);
-        du = du + ay * (Y[c0 + sy] - Y[c0]);
-        du = du + az * (Z[c0 + sz] - Z[c0]);
-        Uo[v] = o.U[v * g.cs + c0];
-        Us[v] = Uo[v] - du;
-    }
-    const double h = 0.5 * dt;
-    const double gg[3] = {gx, gy, gz};
-#pragma unroll
-    for (int e = 0; e < 3; ++e)
-        if (gg[e] != 0.0) {
-            double hg = h * gg[e];
-            double mnew = Us[1 + e] + hg * (Uo[0] + Us[0]);
-            Us[4] = Us[4] + hg * (Uo[1 + e] + mnew);
-            Us[1 + e] = mnew;
-        }
-    int err = 0;
-    Prim q = prim_of(Us[0], Us[1], Us[2], Us[3], Us[4], gm1);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        if (!isfinite(Us[v])) err |= HYDRO_ERR_NONFINITE;
-        o.Un[v * g.cs + c0] = Us[v];
-    }
-    if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
-    if (q.p <= 0.0) err |= HYDRO_ERR_P;
-    if (err) atomicOr(err_dev, err);
-}
+#include "flux_fused.h"
 
 // ---------------------------------------------------------------- host side
 
@@ -615,6 +486,18 @@ bool params_valid(const hydro_params *p)
            isfinite(p->grav[0]) && isfinite(p->grav[1]) && isfinite(p->grav[2]);
 }
 
+// Built-in tile choice for the fused kernels when no tuned table applies:
+// 16 x 16 columns (14 x 14 outputs); z-segments short enough that the box
+// yields at least ~2048 blocks (8 per CU), but no shorter than 8 planes.
+void set_default_tiles(Geo &g)
+{
+    g.tbx = 16;
+    const long long tiles = (long long)((g.n[0] + 13) / 14) * ((g.n[1] + 13) / 14);
+    long long nzs = (2048 + tiles - 1) / tiles;
+    int zs = (int)((g.n[2] + nzs - 1) / nzs);
+    g.tzs = zs < 8 ? 8 : zs;
+}
+
 Geo make_geo(const hydro_box *b)
 {
     Geo g;
@@ -627,6 +510,7 @@ Geo make_geo(const hydro_box *b)
     }
     g.ng = b->ng;
     g.cs = (long long)g.s[0] * g.s[1] * g.s[2];
+    set_default_tiles(g);
     return g;
 }
 
@@ -651,9 +535,8 @@ Launch single(const Geo &g, const double *U, double *Un, void *ws, const double 
 
 // ---------------------------------------------------------------- profiling hook
 
-enum { PG_FILL, PG_DT, PG_PRIM, PG_TRACE, PG_FLUX1, PG_FLUX2, PG_FLUX3, PG_UPDATE, PG_COUNT };
-const char *const kPgNames[PG_COUNT] = {"fill", "dt", "prim", "trace",
-                                        "flux1", "flux2", "flux3", "update"};
+enum { PG_FILL, PG_DT, PG_PRIM, PG_TRACE, PG_FLUX1, PG_FUSED, PG_COUNT };
+const char *const kPgNames[PG_COUNT] = {"fill", "dt", "prim", "trace", "flux1", "corner_final_update"};
 hipEvent_t g_ev[2 * PG_COUNT];
 bool g_ev_on = false;
 
@@ -694,23 +577,10 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
     hipLaunchKernelGGL(k_flux1<1>, set(ST_F1 + 1), blk, 0, st, L, gamma);
     hipLaunchKernelGGL(k_flux1<2>, set(ST_F1 + 2), blk, 0, st, L, gamma);
     prof(PG_FLUX1, 1, st);
-    prof(PG_FLUX2, 0, st);
-    hipLaunchKernelGGL((k_flux2<0, 1>), set(ST_F2 + FAM(0, 1)), blk, 0, st, L, gamma, err_dev);
-    hipLaunchKernelGGL((k_flux2<0, 2>), set(ST_F2 + FAM(0, 2)), blk, 0, st, L, gamma, err_dev);
-    hipLaunchKernelGGL((k_flux2<1, 0>), set(ST_F2 + FAM(1, 0)), blk, 0, st, L, gamma, err_dev);
-    hipLaunchKernelGGL((k_flux2<1, 2>), set(ST_F2 + FAM(1, 2)), blk, 0, st, L, gamma, err_dev);
-    hipLaunchKernelGGL((k_flux2<2, 0>), set(ST_F2 + FAM(2, 0)), blk, 0, st, L, gamma, err_dev);
-    hipLaunchKernelGGL((k_flux2<2, 1>), set(ST_F2 + FAM(2, 1)), blk, 0, st, L, gamma, err_dev);
-    prof(PG_FLUX2, 1, st);
-    prof(PG_FLUX3, 0, st);
-    hipLaunchKernelGGL(k_flux3<0>, set(ST_F3 + 0), blk, 0, st, L, gamma, err_dev);
-    hipLaunchKernelGGL(k_flux3<1>, set(ST_F3 + 1), blk, 0, st, L, gamma, err_dev);
-    hipLaunchKernelGGL(k_flux3<2>, set(ST_F3 + 2), blk, 0, st, L, gamma, err_dev);
-    prof(PG_FLUX3, 1, st);
-    prof(PG_UPDATE, 0, st);
-    hipLaunchKernelGGL(k_update, set(ST_UPD), blk, 0, st, L, gamma, prm->grav[0],
+    prof(PG_FUSED, 0, st);
+    hipLaunchKernelGGL(k_flux_fused, set(ST_FUSED), dim3(kFT), 0, st, L, gamma, prm->grav[0],
                        prm->grav[1], prm->grav[2], err_dev);
-    prof(PG_UPDATE, 1, st);
+    prof(PG_FUSED, 1, st);
     return launch_status();
 }
 
