@@ -151,13 +151,16 @@ int orc_fill_ghosts(double *U, const orc_box *b)
 /* A1: equation of state and variable changes                          */
 /* ------------------------------------------------------------------ */
 
-/* (rho,u,v,w,p) and the sound speed c from conserved variables */
+/* (rho,u,v,w,p) and the sound speed c from conserved variables.  The
+ * reciprocal of the density is formed once and multiplies, as do 1/(gamma-1)
+ * and 1/c^2 below: one division per state instead of one per use. */
 static void prim_c(const double U[5], double gamma, double gm1, double q[6])
 {
     double rho = U[0];
-    double u = U[1] / rho;
-    double v = U[2] / rho;
-    double w = U[3] / rho;
+    double rinv = 1.0 / rho;
+    double u = U[1] * rinv;
+    double v = U[2] * rinv;
+    double w = U[3] * rinv;
     double ke = (0.5 * rho) * ((u * u + v * v) + w * w);
     double p = gm1 * (U[4] - ke);
     q[0] = rho;
@@ -165,7 +168,7 @@ static void prim_c(const double U[5], double gamma, double gm1, double q[6])
     q[2] = v;
     q[3] = w;
     q[4] = p;
-    q[5] = sqrt((gamma * p) / rho);
+    q[5] = sqrt((gamma * p) * rinv);
 }
 
 void orc_prim_of_cons(const double U[5], double gamma, double q[5])
@@ -178,11 +181,12 @@ void orc_prim_of_cons(const double U[5], double gamma, double q[5])
 static void cons_of(const double q[5], double gm1, double U[5])
 {
     double rho = q[0], u = q[1], v = q[2], w = q[3], p = q[4];
+    double igm1 = 1.0 / gm1;
     U[0] = rho;
     U[1] = rho * u;
     U[2] = rho * v;
     U[3] = rho * w;
-    U[4] = p / gm1 + (0.5 * rho) * ((u * u + v * v) + w * w);
+    U[4] = p * igm1 + (0.5 * rho) * ((u * u + v * v) + w * w);
 }
 
 void orc_cons_of_prim(const double q[5], double gamma, double U[5])
@@ -331,7 +335,8 @@ static void trace_cell(const double q[5][5], double c, int d, double dtdx,
 
     const double rc = rho * c;
     const double cs2 = c * c;
-    const double cor = c / rho;
+    const double ics2 = 1.0 / cs2;
+    const double cor = c * (1.0 / rho);
     double f[5];
 
     /* high face: reference = + wave */
@@ -341,8 +346,8 @@ static void trace_cell(const double q[5][5], double c, int d, double dtdx,
         double dpm = r_p - Ip[4][0];
         double drz = r_rho - Ip[0][1];
         double dpz = r_p - Ip[4][1];
-        double am = lam[0] > 0.0 ? (0.5 * (dpm - rc * dum)) / cs2 : 0.0;
-        double az = lam[1] > 0.0 ? drz - dpz / cs2 : 0.0;
+        double am = lam[0] > 0.0 ? (0.5 * (dpm - rc * dum)) * ics2 : 0.0;
+        double az = lam[1] > 0.0 ? drz - dpz * ics2 : 0.0;
         f[0] = r_rho - (am + az);
         f[1] = r_un + cor * am;
         f[2] = lam[1] > 0.0 ? Ip[2][1] : Ip[2][2];
@@ -357,8 +362,8 @@ static void trace_cell(const double q[5][5], double c, int d, double dtdx,
         double dpp = r_p - Im[4][2];
         double drz = r_rho - Im[0][1];
         double dpz = r_p - Im[4][1];
-        double ap = lam[2] < 0.0 ? (0.5 * (dpp + rc * dup)) / cs2 : 0.0;
-        double az = lam[1] < 0.0 ? drz - dpz / cs2 : 0.0;
+        double ap = lam[2] < 0.0 ? (0.5 * (dpp + rc * dup)) * ics2 : 0.0;
+        double az = lam[1] < 0.0 ? drz - dpz * ics2 : 0.0;
         f[0] = r_rho - (az + ap);
         f[1] = r_un - cor * ap;
         f[2] = lam[1] < 0.0 ? Im[2][1] : Im[2][0];
@@ -371,7 +376,7 @@ static void trace_cell(const double q[5][5], double c, int d, double dtdx,
 void orc_trace(const double q5[5][5], int d, double gamma, double dtdx,
                double qhi[5], double qlo[5])
 {
-    double c = sqrt((gamma * q5[2][4]) / q5[2][0]);
+    double c = sqrt((gamma * q5[2][4]) * (1.0 / q5[2][0]));
     trace_cell(q5, c, d, dtdx, qhi, qlo);
 }
 
@@ -413,7 +418,7 @@ static void star_flux(const double q[5], double E, int d, double SK, double Ss,
 
 static double total_energy(const double q[5], double gm1)
 {
-    return q[4] / gm1 + (0.5 * q[0]) * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
+    return q[4] * (1.0 / gm1) + (0.5 * q[0]) * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
 }
 
 static void hllc(const double qL[5], const double qR[5], int d, double gamma,
@@ -495,9 +500,10 @@ static int accept_state(const double V[5], const double q[5], double gm1,
                         double out[5])
 {
     double rho = V[0];
-    double u = V[1] / rho;
-    double v = V[2] / rho;
-    double w = V[3] / rho;
+    double rinv = 1.0 / rho;
+    double u = V[1] * rinv;
+    double v = V[2] * rinv;
+    double w = V[3] * rinv;
     double ke = (0.5 * rho) * ((u * u + v * v) + w * w);
     double p = gm1 * (V[4] - ke);
     if (rho <= 0.0 || p <= 0.0) {

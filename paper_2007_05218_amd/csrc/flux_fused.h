@@ -94,9 +94,9 @@ __device__ __forceinline__ Flux load_flux(const WS &ws, int base, long long o)
 
 // corner state: prim(U(q) - fac * dF), with the rejection rule
 __device__ __forceinline__ Face corner_state(const Face &q, const Flux &dF, double fac,
-                                             double gm1, int &fb)
+                                             double gm1, double igm1, int &fb)
 {
-    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
+    const double E = energy(q.r, q.u, q.v, q.w, q.p, igm1);
     double V0 = q.r - fac * dF.m;
     double V1 = (q.r * q.u) - fac * dF.mu;
     double V2 = (q.r * q.v) - fac * dF.mv;
@@ -108,9 +108,10 @@ __device__ __forceinline__ Face corner_state(const Face &q, const Flux &dF, doub
 
 // final state: prim((U(q) - f1 * dA) - f2 * dB), with the rejection rule
 __device__ __forceinline__ Face final_state2(const Face &q, const Flux &dA, const Flux &dB,
-                                             double f1, double f2, double gm1, int &fb)
+                                             double f1, double f2, double gm1, double igm1,
+                                             int &fb)
 {
-    const double E = energy(q.r, q.u, q.v, q.w, q.p, gm1);
+    const double E = energy(q.r, q.u, q.v, q.w, q.p, igm1);
     double V0 = (q.r - f1 * dA.m) - f2 * dB.m;
     double V1 = ((q.r * q.u) - f1 * dA.mu) - f2 * dB.mu;
     double V2 = ((q.r * q.v) - f1 * dA.mv) - f2 * dB.mv;
@@ -187,6 +188,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     const bool outc = tx >= 1 && tx <= T.TX && ty >= 1 && ty <= T.TY && x < n0 && y < n1;
 
     const double gm1 = gamma - 1.0;
+    const double igm1 = 1.0 / gm1;
     const double dt = *o.dt;
     const double fx3 = dt / (3.0 * g.dx[0]), fy3 = dt / (3.0 * g.dx[1]),
                  fz3 = dt / (3.0 * g.dx[2]);
@@ -217,16 +219,16 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
         // ---------------------------------------------------- A: high corner states
         int fb;
         {
-            Face h = corner_state(qx_hi, dF1y, fy3, gm1, fb);  // (x|y)
+            Face h = corner_state(qx_hi, dF1y, fy3, gm1, igm1, fb);  // (x|y)
             if (fb && hasR && inr(x + 1, 0, n0) && inr(y, 0, n1 - 1) && inr(q, -1, n2)) err |= fb;
             putF(xa.v, 0, t, h);
-            h = corner_state(qy_hi, dF1x, fx3, gm1, fb);  // (y|x)
+            h = corner_state(qy_hi, dF1x, fx3, gm1, igm1, fb);  // (y|x)
             if (fb && hasU && inr(y + 1, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
             putF(xa.v, 5, t, h);
-            h = corner_state(qx_hi, dF1z, fz3, gm1, fb);  // (x|z)
+            h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
             if (fb && hasR && inr(x + 1, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
             putF(xb.v, 0, t, h);
-            h = corner_state(qy_hi, dF1z, fz3, gm1, fb);  // (y|z)
+            h = corner_state(qy_hi, dF1z, fz3, gm1, igm1, fb);  // (y|z)
             if (fb && hasU && inr(y + 1, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
             putF(xb.v, 5, t, h);
         }
@@ -234,33 +236,33 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
         // ---------------------------------------------------- B: round-2 fluxes
         Flux F2xy, F2yx, F2xz, F2yz;
         {
-            Face l = corner_state(qx_lo, dF1y, fy3, gm1, fb);
+            Face l = corner_state(qx_lo, dF1y, fy3, gm1, igm1, fb);
             if (fb && hasL && inr(x, 0, n0) && inr(y, 0, n1 - 1) && inr(q, -1, n2)) err |= fb;
-            F2xy = hllc(getF(xa.v, 0, tL), l, 0, gamma, gm1);
-            l = corner_state(qy_lo, dF1x, fx3, gm1, fb);
+            F2xy = hllc(getF(xa.v, 0, tL), l, 0, gamma, igm1);
+            l = corner_state(qy_lo, dF1x, fx3, gm1, igm1, fb);
             if (fb && hasD && inr(y, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
-            F2yx = hllc(getF(xa.v, 5, tD), l, 1, gamma, gm1);
-            l = corner_state(qx_lo, dF1z, fz3, gm1, fb);
+            F2yx = hllc(getF(xa.v, 5, tD), l, 1, gamma, igm1);
+            l = corner_state(qx_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && hasL && inr(x, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
-            F2xz = hllc(getF(xb.v, 0, tL), l, 0, gamma, gm1);
-            l = corner_state(qy_lo, dF1z, fz3, gm1, fb);
+            F2xz = hllc(getF(xb.v, 0, tL), l, 0, gamma, igm1);
+            l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && hasD && inr(y, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
-            F2yz = hllc(getF(xb.v, 5, tD), l, 1, gamma, gm1);
+            F2yz = hllc(getF(xb.v, 5, tD), l, 1, gamma, igm1);
         }
         // z-families: the flux through the z-face between q-1 and q
         {
             const bool valid = q >= T.z0;  // the plane below was computed here
-            Face l = corner_state(qz_lo, dF1x, fx3, gm1, fb);  // (z|x)
+            Face l = corner_state(qz_lo, dF1x, fx3, gm1, igm1, fb);  // (z|x)
             if (fb && valid && inr(q, 0, n2) && inr(x, 0, n0 - 1) && inr(y, -1, n1)) err |= fb;
-            Flux Fzx = hllc(c_zx_hi, l, 2, gamma, gm1);
-            Face h = corner_state(qz_hi, dF1x, fx3, gm1, fb);
+            Flux Fzx = hllc(c_zx_hi, l, 2, gamma, igm1);
+            Face h = corner_state(qz_hi, dF1x, fx3, gm1, igm1, fb);
             if (fb && q + 1 <= T.z1 && inr(q + 1, 0, n2) && inr(x, 0, n0 - 1) && inr(y, -1, n1))
                 err |= fb;
             c_zx_hi = h;
-            l = corner_state(qz_lo, dF1y, fy3, gm1, fb);  // (z|y)
+            l = corner_state(qz_lo, dF1y, fy3, gm1, igm1, fb);  // (z|y)
             if (fb && valid && inr(q, 0, n2) && inr(y, 0, n1 - 1) && inr(x, -1, n0)) err |= fb;
-            Flux Fzy = hllc(c_zy_hi, l, 2, gamma, gm1);
-            h = corner_state(qz_hi, dF1y, fy3, gm1, fb);
+            Flux Fzy = hllc(c_zy_hi, l, 2, gamma, igm1);
+            h = corner_state(qz_hi, dF1y, fy3, gm1, igm1, fb);
             if (fb && q + 1 <= T.z1 && inr(q + 1, 0, n2) && inr(y, 0, n1 - 1) && inr(x, -1, n0))
                 err |= fb;
             c_zy_hi = h;
@@ -280,11 +282,11 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             const Flux dxy = fdiff(getX(xa.v, 0, tR), F2xy);
             const Flux dyx = fdiff(getX(xa.v, 5, tU), F2yx);
             const bool zin = hasL && hasR && hasD && hasU && x < n0 && y < n1;
-            Face zl = final_state2(qz_lo, dxy, dyx, fx2, fy2, gm1, fb);
+            Face zl = final_state2(qz_lo, dxy, dyx, fx2, fy2, gm1, igm1, fb);
             if (fb && zin && inr(q, 0, n2) && q >= T.z0 && x >= 0 && y >= 0) err |= fb;
-            Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, fb);
+            Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, igm1, fb);
             if (fb && zin && inr(q + 1, 0, n2) && q + 1 <= T.z1 && x >= 0 && y >= 0) err |= fb;
-            Flux F3zq = hllc(fz_hi, zl, 2, gamma, gm1);
+            Flux F3zq = hllc(fz_hi, zl, 2, gamma, igm1);
             fz_hi = zh;
             // differences of the in-plane (s|z) fluxes of plane q (used next plane)
             const Flux dxz = fdiff(getX(xb.v, 0, tR), F2xz);
@@ -296,22 +298,22 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             Face xl, xh, yl, yh;
             {
                 const Face a = load_face(ws, QLO(0, 0), op), b = load_face(ws, QHI(0, 0), op);
-                xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, fb);
+                xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
                 if (fb && pv && hasL && hasD && hasU && inr(x, 0, n0) && inr(y, 0, n1 - 1) &&
                     inr(p, 0, n2 - 1))
                     err |= fb;
-                xh = final_state2(b, dF2yz, dzy, fy2, fz2, gm1, fb);
+                xh = final_state2(b, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
                 if (fb && pv && hasR && hasD && hasU && inr(x + 1, 0, n0) && inr(y, 0, n1 - 1) &&
                     inr(p, 0, n2 - 1))
                     err |= fb;
             }
             {
                 const Face a = load_face(ws, QLO(1, 0), op), b = load_face(ws, QHI(1, 0), op);
-                yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, fb);
+                yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
                 if (fb && pv && hasD && hasL && hasR && inr(y, 0, n1) && inr(x, 0, n0 - 1) &&
                     inr(p, 0, n2 - 1))
                     err |= fb;
-                yh = final_state2(b, dF2xz, dzx, fx2, fz2, gm1, fb);
+                yh = final_state2(b, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
                 if (fb && pv && hasU && hasL && hasR && inr(y + 1, 0, n1) && inr(x, 0, n0 - 1) &&
                     inr(p, 0, n2 - 1))
                     err |= fb;
@@ -323,8 +325,8 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             putF(xa.v, 0, t, xh);
             putF(xa.v, 5, t, yh);
             __syncthreads();
-            const Flux F3x = hllc(getF(xa.v, 0, tL), xl, 0, gamma, gm1);
-            const Flux F3y = hllc(getF(xa.v, 5, tD), yl, 1, gamma, gm1);
+            const Flux F3x = hllc(getF(xa.v, 0, tL), xl, 0, gamma, igm1);
+            const Flux F3y = hllc(getF(xa.v, 5, tD), yl, 1, gamma, igm1);
             putX(xb.v, 0, t, F3x);
             putX(xb.v, 5, t, F3y);
             __syncthreads();

@@ -53,18 +53,16 @@ struct Geo {
     int tzs;  // fused kernels: z-segment length per block
 };
 
-// workspace fields
-constexpr int P_R = 0, P_U = 1, P_V = 2, P_W = 3, P_P = 4, P_C = 5;
-__host__ __device__ constexpr int QHI(int d, int v) { return 6 + d * 10 + v; }
-__host__ __device__ constexpr int QLO(int d, int v) { return 6 + d * 10 + 5 + v; }
-__host__ __device__ constexpr int F1F(int d, int v) { return 36 + d * 5 + v; }
-__host__ __device__ constexpr int FAM(int t, int s) { return t * 2 + (s < t ? s : s - 1); }
-__host__ __device__ constexpr int F2F(int fam, int v) { return 51 + fam * 5 + v; }
-__host__ __device__ constexpr int F3F(int d, int v) { return 81 + d * 5 + v; }
-constexpr int kFields = 96;
+// workspace fields: traced face states (direction d, high/low face,
+// component v) and round-1 fluxes (face normal d, component v), each a dense
+// ghosted array like one state component
+__host__ __device__ constexpr int QHI(int d, int v) { return d * 10 + v; }
+__host__ __device__ constexpr int QLO(int d, int v) { return d * 10 + 5 + v; }
+__host__ __device__ constexpr int F1F(int d, int v) { return 30 + d * 5 + v; }
+constexpr int kFields = 45;
 
 // stages (block-count prefix arrays are kept per stage)
-enum { ST_FILL = 0, ST_DT = 1, ST_PRIM = 2, ST_TRACE = 3, ST_F1 = 4, ST_FUSED = 7, ST_COUNT = 8 };
+enum { ST_FILL = 0, ST_DT = 1, ST_TRACE = 2, ST_FLUX = 3, ST_COUNT = 4 };
 constexpr int kDtCellsPerThread = 4;
 constexpr long long kDtMaxBlocks = 4096;
 
@@ -94,28 +92,6 @@ struct Reg {
     int ext[3];
 };
 
-// index region of a stage (cells; a face f along d is stored at cell f)
-__host__ __device__ inline Reg stage_reg(const Geo &g, int st)
-{
-    Reg r;
-    const int *n = g.n;
-    int lo[3] = {0, 0, 0}, hi[3] = {n[0], n[1], n[2]};
-    if (st == ST_PRIM) {
-        for (int e = 0; e < 3; ++e) { lo[e] = -g.ng; hi[e] = n[e] + g.ng; }
-    } else if (st == ST_TRACE) {
-        for (int e = 0; e < 3; ++e) { lo[e] = -1; hi[e] = n[e] + 1; }
-    } else if (st >= ST_F1 && st < ST_F1 + 3) {
-        int d = st - ST_F1;
-        for (int e = 0; e < 3; ++e) { lo[e] = -1; hi[e] = n[e] + 1; }
-        lo[d] = 0;
-    }
-    for (int e = 0; e < 3; ++e) {
-        r.lo[e] = lo[e];
-        r.ext[e] = hi[e] - lo[e];
-    }
-    return r;
-}
-
 __host__ __device__ inline long long reg_count(const Reg &r)
 {
     return (long long)r.ext[0] * r.ext[1] * r.ext[2];
@@ -131,23 +107,21 @@ __device__ __forceinline__ bool reg_cell(const Reg &r, long long t, int &i, int 
     return true;
 }
 
-// work items of a stage for one box
-__host__ inline long long stage_items(const Geo &g, int st)
-{
-    long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
-    if (st == ST_FILL) return g.cs - nv;
-    if (st == ST_DT) return nv;
-    return reg_count(stage_reg(g, st));
-}
-
+// blocks of one box in a stage
 __host__ inline long long stage_blocks(const Geo &g, int st)
 {
-    if (st == ST_FUSED) {  // tiles of (tbx-2) x (256/tbx-2) columns by z-segments of tzs
+    if (st == ST_TRACE) {  // tiles of (tbx-1) x (256/tbx-1) columns over [-1, n+1)
+        const long long TX = g.tbx - 1, TY = 256 / g.tbx - 1;
+        return ((g.n[0] + 2 + TX - 1) / TX) * ((g.n[1] + 2 + TY - 1) / TY) *
+               ((g.n[2] + 2 + g.tzs - 1) / g.tzs);
+    }
+    if (st == ST_FLUX) {  // tiles of (tbx-2) x (256/tbx-2) columns over [0, n)
         const long long TX = g.tbx - 2, TY = 256 / g.tbx - 2;
         return ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) *
                ((g.n[2] + g.tzs - 1) / g.tzs);
     }
-    long long items = stage_items(g, st);
+    const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
+    long long items = st == ST_FILL ? g.cs - nv : nv;
     if (st == ST_DT) {
         long long b = (items + (long long)kBlock * kDtCellsPerThread - 1) /
                       ((long long)kBlock * kDtCellsPerThread);
@@ -325,7 +299,7 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
         long long c0 = cell(g, i, j, k);
         Prim q = prim_of(U[c0], U[g.cs + c0], U[2 * g.cs + c0], U[3 * g.cs + c0],
                          U[4 * g.cs + c0], gm1);
-        double c = sound(gamma, q.p, q.r);
+        double c = sound_ri(gamma, q.p, q.ri);
         double a = g.dx[0] / (fabs(q.u) + c);
         double b = g.dx[1] / (fabs(q.v) + c);
         double e = g.dx[2] / (fabs(q.w) + c);
@@ -345,80 +319,6 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
         atomicMin(dt_bits + o.b, v);
         if (dtmin_bits) atomicMin(dtmin_bits, v);
     }
-}
-
-// ---------------------------------------------------------------- prim
-
-__global__ void __launch_bounds__(kBlock) k_prim(Launch L, double gamma)
-{
-    Box1 o = resolve(L);
-    const Geo &g = o.g;
-    long long t = o.blk * kBlock + threadIdx.x;
-    if (t >= g.cs) return;
-    const double *U = o.U;
-    Prim q = prim_of(U[t], U[g.cs + t], U[2 * g.cs + t], U[3 * g.cs + t], U[4 * g.cs + t],
-                     gamma - 1.0);
-    o.ws.f(P_R)[t] = q.r;
-    o.ws.f(P_U)[t] = q.u;
-    o.ws.f(P_V)[t] = q.v;
-    o.ws.f(P_W)[t] = q.w;
-    o.ws.f(P_P)[t] = q.p;
-    o.ws.f(P_C)[t] = sound(gamma, q.p, q.r);
-}
-
-// ---------------------------------------------------------------- trace
-
-// every direction index below is a compile-time constant, so the box
-// descriptor stays in registers (a runtime index into it would put the
-// descriptor in per-lane scratch memory)
-template <int d>
-__device__ __forceinline__ void trace_body(const Launch &L, double gx, double gy, double gz)
-{
-    Box1 o = resolve(L);
-    const Geo &g = o.g;
-    int i, j, k;
-    if (!reg_cell(stage_reg(g, ST_TRACE), o.blk * kBlock + threadIdx.x, i, j, k)) return;
-    const WS &ws = o.ws;
-    const double dt = *o.dt;
-    const double dtdx = dt / g.dx[d];
-    const long long c0 = cell(g, i, j, k);
-    const long long sd = stride(g, d);
-    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    const double *R = ws.f(P_R), *P = ws.f(P_P);
-    const double *Un = ws.f(P_U + d), *T1 = ws.f(P_U + t1), *T2 = ws.f(P_U + t2);
-    double rs[5], uns[5], t1s[5], t2s[5], ps[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-        long long oo = c0 + (m - 2) * sd;
-        rs[m] = R[oo];
-        uns[m] = Un[oo];
-        t1s[m] = T1[oo];
-        t2s[m] = T2[oo];
-        ps[m] = P[oo];
-    }
-    Face hi, lo;
-    trace_cell(rs, uns, t1s, t2s, ps, ws.f(P_C)[c0], d, dtdx, hi, lo);
-    const double h = 0.5 * dt;
-    if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
-    if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
-    if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
-    ws.f(QHI(d, 0))[c0] = hi.r;
-    ws.f(QHI(d, 1))[c0] = hi.u;
-    ws.f(QHI(d, 2))[c0] = hi.v;
-    ws.f(QHI(d, 3))[c0] = hi.w;
-    ws.f(QHI(d, 4))[c0] = hi.p;
-    ws.f(QLO(d, 0))[c0] = lo.r;
-    ws.f(QLO(d, 1))[c0] = lo.u;
-    ws.f(QLO(d, 2))[c0] = lo.v;
-    ws.f(QLO(d, 3))[c0] = lo.w;
-    ws.f(QLO(d, 4))[c0] = lo.p;
-}
-
-__global__ void __launch_bounds__(kBlock) k_trace(Launch L, double gx, double gy, double gz)
-{
-    if (blockIdx.y == 0) trace_body<0>(L, gx, gy, gz);
-    else if (blockIdx.y == 1) trace_body<1>(L, gx, gy, gz);
-    else trace_body<2>(L, gx, gy, gz);
 }
 
 __device__ __forceinline__ Face load_face(const WS &ws, int base, long long o)
@@ -441,22 +341,8 @@ __device__ __forceinline__ void store_flux(const WS &ws, int base, long long o, 
     ws.f(base + 4)[o] = F.e;
 }
 
-// ---------------------------------------------------------------- flux1
-
-template <int d>
-__global__ void __launch_bounds__(kBlock) k_flux1(Launch L, double gamma)
-{
-    Box1 o = resolve(L);
-    const Geo &g = o.g;
-    int i, j, k;
-    if (!reg_cell(stage_reg(g, ST_F1 + d), o.blk * kBlock + threadIdx.x, i, j, k)) return;
-    const long long c0 = cell(g, i, j, k);
-    Face Lf = load_face(o.ws, QHI(d, 0), c0 - stride(g, d));
-    Face Rf = load_face(o.ws, QLO(d, 0), c0);
-    store_flux(o.ws, F1F(d, 0), c0, hllc(Lf, Rf, d, gamma, gamma - 1.0));
-}
-
 #include "flux_fused.h"
+#include "trace_fused.h"
 
 // ---------------------------------------------------------------- host side
 
@@ -498,6 +384,8 @@ void set_default_tiles(Geo &g)
     g.tzs = zs < 8 ? 8 : zs;
 }
 
+bool tiles_valid(int tbx, int tzs) { return (tbx == 8 || tbx == 16 || tbx == 32) && tzs >= 1; }
+
 Geo make_geo(const hydro_box *b)
 {
     Geo g;
@@ -535,8 +423,8 @@ Launch single(const Geo &g, const double *U, double *Un, void *ws, const double 
 
 // ---------------------------------------------------------------- profiling hook
 
-enum { PG_FILL, PG_DT, PG_PRIM, PG_TRACE, PG_FLUX1, PG_FUSED, PG_COUNT };
-const char *const kPgNames[PG_COUNT] = {"fill", "dt", "prim", "trace", "flux1", "corner_final_update"};
+enum { PG_FILL, PG_DT, PG_TRACE, PG_FUSED, PG_COUNT };
+const char *const kPgNames[PG_COUNT] = {"fill", "dt", "trace_flux1", "corner_final_update"};
 hipEvent_t g_ev[2 * PG_COUNT];
 bool g_ev_on = false;
 
@@ -560,25 +448,12 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
         if (L.nb) L.pre = pre[stage];
         return dim3((unsigned)grid[stage]);
     };
-    dim3 blk(kBlock);
-    prof(PG_PRIM, 0, st);
-    hipLaunchKernelGGL(k_prim, set(ST_PRIM), blk, 0, st, L, gamma);
-    prof(PG_PRIM, 1, st);
     prof(PG_TRACE, 0, st);
-    {
-        dim3 gr = set(ST_TRACE);
-        gr.y = 3;
-        hipLaunchKernelGGL(k_trace, gr, blk, 0, st, L, prm->grav[0], prm->grav[1],
-                           prm->grav[2]);
-    }
+    hipLaunchKernelGGL(k_trace_fused, set(ST_TRACE), dim3(kTT), 0, st, L, gamma, prm->grav[0],
+                       prm->grav[1], prm->grav[2]);
     prof(PG_TRACE, 1, st);
-    prof(PG_FLUX1, 0, st);
-    hipLaunchKernelGGL(k_flux1<0>, set(ST_F1 + 0), blk, 0, st, L, gamma);
-    hipLaunchKernelGGL(k_flux1<1>, set(ST_F1 + 1), blk, 0, st, L, gamma);
-    hipLaunchKernelGGL(k_flux1<2>, set(ST_F1 + 2), blk, 0, st, L, gamma);
-    prof(PG_FLUX1, 1, st);
     prof(PG_FUSED, 0, st);
-    hipLaunchKernelGGL(k_flux_fused, set(ST_FUSED), dim3(kFT), 0, st, L, gamma, prm->grav[0],
+    hipLaunchKernelGGL(k_flux_fused, set(ST_FLUX), dim3(kFT), 0, st, L, gamma, prm->grav[0],
                        prm->grav[1], prm->grav[2], err_dev);
     prof(PG_FUSED, 1, st);
     return launch_status();

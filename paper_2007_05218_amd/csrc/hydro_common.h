@@ -27,9 +27,11 @@ __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : 
 
 // ---------------------------------------------------------------- EOS
 
-// (rho, u, v, w, p) of a conserved state
+// (rho, u, v, w, p) of a conserved state, and 1/rho.  The reciprocal of the
+// density is formed once per state and multiplies (likewise 1/(gamma-1) and
+// 1/c^2): FP64 division is a ten-instruction sequence on gfx950.
 struct Prim {
-    double r, u, v, w, p;
+    double r, u, v, w, p, ri;
 };
 
 __device__ __forceinline__ Prim prim_of(double U0, double U1, double U2, double U3,
@@ -37,24 +39,32 @@ __device__ __forceinline__ Prim prim_of(double U0, double U1, double U2, double 
 {
     Prim q;
     q.r = U0;
-    q.u = U1 / U0;
-    q.v = U2 / U0;
-    q.w = U3 / U0;
+    q.ri = 1.0 / U0;
+    q.u = U1 * q.ri;
+    q.v = U2 * q.ri;
+    q.w = U3 * q.ri;
     double ke = (0.5 * q.r) * ((q.u * q.u + q.v * q.v) + q.w * q.w);
     q.p = gm1 * (U4 - ke);
     return q;
 }
 
+// sound speed of a cell state (its 1/rho known)
+__device__ __forceinline__ double sound_ri(double gamma, double p, double ri)
+{
+    return sqrt((gamma * p) * ri);
+}
+
+// sound speed of a face state (HLLC input)
 __device__ __forceinline__ double sound(double gamma, double p, double r)
 {
     return sqrt((gamma * p) / r);
 }
 
-// total energy density of a primitive state
+// total energy density of a primitive state; igm1 = 1/(gamma-1)
 __device__ __forceinline__ double energy(double r, double u, double v, double w,
-                                         double p, double gm1)
+                                         double p, double igm1)
 {
-    return p / gm1 + (0.5 * r) * ((u * u + v * v) + w * w);
+    return p * igm1 + (0.5 * r) * ((u * u + v * v) + w * w);
 }
 
 // velocity component a (0,1,2) of a primitive state
@@ -155,7 +165,7 @@ __device__ __forceinline__ void set_lab(Face &f, int d, double r, double un, dou
 
 __device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (&uns)[5],
                                            const double (&t1s)[5], const double (&t2s)[5],
-                                           const double (&ps)[5], double c, int d,
+                                           const double (&ps)[5], double c, double ri, int d,
                                            double dtdx, Face &hi, Face &lo)
 {
     const double rho = rs[2];
@@ -168,7 +178,8 @@ __device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (
     Parab Pp = ppm(ps[0], ps[1], ps[2], ps[3], ps[4]);
     const double rc = rho * c;
     const double cs2 = c * c;
-    const double cor = c / rho;
+    const double ics2 = 1.0 / cs2;
+    const double cor = c * ri;
 
     {  // high face, reference = + wave
         double r_r = int_hi(Pr, lp, dtdx);
@@ -178,8 +189,8 @@ __device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (
         double dpm = r_p - int_hi(Pp, lm, dtdx);
         double drz = r_r - int_hi(Pr, l0, dtdx);
         double dpz = r_p - int_hi(Pp, l0, dtdx);
-        double am = lm > 0.0 ? (0.5 * (dpm - rc * dum)) / cs2 : 0.0;
-        double az = l0 > 0.0 ? drz - dpz / cs2 : 0.0;
+        double am = lm > 0.0 ? (0.5 * (dpm - rc * dum)) * ics2 : 0.0;
+        double az = l0 > 0.0 ? drz - dpz * ics2 : 0.0;
         double t1 = l0 > 0.0 ? int_hi(P1, l0, dtdx) : int_hi(P1, lp, dtdx);
         double t2 = l0 > 0.0 ? int_hi(P2, l0, dtdx) : int_hi(P2, lp, dtdx);
         set_lab(hi, d, r_r - (am + az), r_u + cor * am, t1, t2, r_p - cs2 * am);
@@ -192,8 +203,8 @@ __device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (
         double dpp = r_p - int_lo(Pp, lp, dtdx);
         double drz = r_r - int_lo(Pr, l0, dtdx);
         double dpz = r_p - int_lo(Pp, l0, dtdx);
-        double ap = lp < 0.0 ? (0.5 * (dpp + rc * dup)) / cs2 : 0.0;
-        double az = l0 < 0.0 ? drz - dpz / cs2 : 0.0;
+        double ap = lp < 0.0 ? (0.5 * (dpp + rc * dup)) * ics2 : 0.0;
+        double az = l0 < 0.0 ? drz - dpz * ics2 : 0.0;
         double t1 = l0 < 0.0 ? int_lo(P1, l0, dtdx) : int_lo(P1, lm, dtdx);
         double t2 = l0 < 0.0 ? int_lo(P2, l0, dtdx) : int_lo(P2, lm, dtdx);
         set_lab(lo, d, r_r - (az + ap), r_u - cor * ap, t1, t2, r_p - cs2 * ap);
@@ -228,36 +239,15 @@ __device__ __forceinline__ Flux phys_flux(const Face &q, double E, int d)
     return F;
 }
 
-// star flux F_K + S_K (U*_K - U_K) on side K
-__device__ __forceinline__ Flux star_flux(const Face &q, double E, int d, double SK,
-                                          double Ss)
-{
-    const double r = q.r, uK = fvel(q, d), pK = q.p;
-    Flux F = phys_flux(q, E, d);
-    double chi = (SK - uK) / (SK - Ss);
-    double s0 = chi * r;
-    double su = chi * (r * q.u);
-    double sv = chi * (r * q.v);
-    double sw = chi * (r * q.w);
-    if (d == 0) su = chi * (r * Ss);
-    else if (d == 1) sv = chi * (r * Ss);
-    else sw = chi * (r * Ss);
-    double se = chi * (E + (r * (Ss - uK)) * (Ss + pK / (r * (SK - uK))));
-    F.m = F.m + SK * (s0 - r);
-    F.mu = F.mu + SK * (su - r * q.u);
-    F.mv = F.mv + SK * (sv - r * q.v);
-    F.mw = F.mw + SK * (sw - r * q.w);
-    F.e = F.e + SK * (se - E);
-    return F;
-}
-
+// HLLC flux through a d-face.  The four cases (left state, left star, right
+// star, right state) are decided first; then only the chosen side's energy,
+// physical flux and (if needed) star correction F_K + S_K (U*_K - U_K) are
+// evaluated, each with exactly the arithmetic of its case.
 __device__ __forceinline__ Flux hllc(const Face &L, const Face &R, int d, double gamma,
-                                     double gm1)
+                                     double igm1)
 {
     const double rL = L.r, uL = fvel(L, d), pL = L.p;
     const double rR = R.r, uR = fvel(R, d), pR = R.p;
-    const double EL = energy(L.r, L.u, L.v, L.w, L.p, gm1);
-    const double ER = energy(R.r, R.u, R.v, R.w, R.p, gm1);
     const double cL = sound(gamma, pL, rL);
     const double cR = sound(gamma, pR, rR);
     const double SL = dmin(uL - cL, uR - cR);
@@ -265,10 +255,36 @@ __device__ __forceinline__ Flux hllc(const Face &L, const Face &R, int d, double
     const double num = ((pR - pL) + (rL * uL) * (SL - uL)) - (rR * uR) * (SR - uR);
     const double den = rL * (SL - uL) - rR * (SR - uR);
     const double Ss = num / den;
-    if (0.0 <= SL) return phys_flux(L, EL, d);
-    if (0.0 <= Ss) return star_flux(L, EL, d, SL, Ss);
-    if (0.0 < SR) return star_flux(R, ER, d, SR, Ss);
-    return phys_flux(R, ER, d);
+    const bool sL = 0.0 <= SL, sS = 0.0 <= Ss, sR = 0.0 < SR;
+    const bool left = sL || sS;
+    const bool star = !sL && (sS || sR);
+    Face K;
+    K.r = left ? L.r : R.r;
+    K.u = left ? L.u : R.u;
+    K.v = left ? L.v : R.v;
+    K.w = left ? L.w : R.w;
+    K.p = left ? L.p : R.p;
+    const double SK = left ? SL : SR;
+    const double E = energy(K.r, K.u, K.v, K.w, K.p, igm1);
+    Flux F = phys_flux(K, E, d);
+    if (star) {
+        const double r = K.r, uK = fvel(K, d), pK = K.p;
+        double chi = (SK - uK) / (SK - Ss);
+        double s0 = chi * r;
+        double su = chi * (r * K.u);
+        double sv = chi * (r * K.v);
+        double sw = chi * (r * K.w);
+        if (d == 0) su = chi * (r * Ss);
+        else if (d == 1) sv = chi * (r * Ss);
+        else sw = chi * (r * Ss);
+        double se = chi * (E + (r * (Ss - uK)) * (Ss + pK / (r * (SK - uK))));
+        F.m = F.m + SK * (s0 - r);
+        F.mu = F.mu + SK * (su - r * K.u);
+        F.mv = F.mv + SK * (sv - r * K.v);
+        F.mw = F.mw + SK * (sw - r * K.w);
+        F.e = F.e + SK * (se - E);
+    }
+    return F;
 }
 
 // ---------------------------------------------------------------- corrections

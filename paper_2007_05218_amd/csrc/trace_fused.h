@@ -1,0 +1,207 @@
+// trace_fused.h -- the first half of the CTU step in one kernel: primitive
+// variables, PPM reconstruction and characteristic tracing in all three
+// directions (with the half-step gravity kick), and the round-1 HLLC fluxes,
+// for one box tile, marching along z.
+//
+// Output (HBM workspace): the traced face states of every cell one beyond
+// the valid region, and the round-1 fluxes at every face the corner step
+// reads -- the inputs of the fused flux kernel.  Each cell's primitives are
+// computed once per block: a plane of the tile plus a two-cell ring enters
+// an LDS ring of three planes (the x/y stencils read the centre plane from
+// it) and each column copies its own values into a five-plane register
+// window for the z stencil.  This is the one-zone-per-thread stencil of the
+// paper's Sec. III with the neighbouring slopes staged on chip instead of
+// recomputed from global memory.
+//
+// Tile: a 256-thread block covers BX x BY columns: output columns
+// [x0, x0+BX-1) x [y0, y0+BY-1) of the traced region plus one column on
+// the low side of each axis, whose high-face state the round-1 flux on the
+// first output column needs.  Blocks march over planes [z0, z1) of the
+// traced region, with one warm-up plane below z0 for the z-face flux.
+#pragma once
+
+namespace {
+
+constexpr int kTT = 256;      // threads of a fused-trace block
+constexpr int kTPlane = 432;  // LDS cells of one plane: (BX+4)(BY+4) <= 432 for BX in {8,16,32}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__global__ void __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(2)))
+k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
+{
+    __shared__ double pl[3][5][kTPlane];  // primitive planes (rho, u, v, w, p), ring of 3
+    __shared__ double xq[10][kTT];        // high-face x and y states for the round-1 fluxes
+    Box1 o = resolve(L);
+    const Geo &g = o.g;
+    const WS &ws = o.ws;
+    const int BX = g.tbx, BY = kTT / g.tbx, TX = BX - 1, TY = BY - 1;
+    const int RW = BX + 4, RH = BY + 4;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], ng = g.ng;
+    // tiles cover the traced region [-1, n+1) of each axis
+    const int ntx = (n0 + 2 + TX - 1) / TX, nty = (n1 + 2 + TY - 1) / TY;
+    long long tt;
+    {
+        long long per = o.nblk / 8, rem = o.nblk % 8;
+        long long xx = o.blk % 8, ii = o.blk / 8;
+        tt = xx * per + (xx < rem ? xx : rem) + ii;
+    }
+    const int ix = (int)(tt % ntx);
+    tt /= ntx;
+    const int iy = (int)(tt % nty);
+    const int iz = (int)(tt / nty);
+    const int x0 = -1 + ix * TX, y0 = -1 + iy * TY;
+    const int z0 = -1 + iz * g.tzs, z1 = min(n2 + 1, z0 + g.tzs);
+
+    const int t = threadIdx.x;
+    const int tx = t % BX, ty = t / BX;
+    const int x = x0 - 1 + tx, y = y0 - 1 + ty;  // this thread's column
+    const bool inner = tx >= 1 && ty >= 1 && x <= n0 && y <= n1;
+    const int tL = tx >= 1 ? t - 1 : t, tD = ty >= 1 ? t - BX : t;
+    const int rc = (ty + 2) * RW + (tx + 2);  // own column in the plane buffer
+
+    const double gm1 = gamma - 1.0;
+    const double igm1 = 1.0 / gm1;
+    const double dt = *o.dt;
+    const double dtdx = dt / g.dx[0], dtdy = dt / g.dx[1], dtdz = dt / g.dx[2];
+    const double h = 0.5 * dt;
+
+    // region plane loader: cells (x0-3 .. x0+TX+1) x (y0-3 .. y0+TY+1) of plane z,
+    // indices clamped into the ghosted box (clamped cells feed only unused lanes)
+    auto load_plane = [&](int z) {
+        const int slot = (z + 6) % 3;
+        const int zc = clampi(z, -ng, n2 + ng - 1);
+        for (int r = t; r < RW * RH; r += kTT) {
+            const int rx = r % RW, ry = r / RW;
+            const int cx = clampi(x0 - 3 + rx, -ng, n0 + ng - 1);
+            const int cy = clampi(y0 - 3 + ry, -ng, n1 + ng - 1);
+            const long long c0 = cell(g, cx, cy, zc);
+            Prim q = prim_of(o.U[c0], o.U[g.cs + c0], o.U[2 * g.cs + c0], o.U[3 * g.cs + c0],
+                             o.U[4 * g.cs + c0], gm1);
+            pl[slot][0][r] = q.r;
+            pl[slot][1][r] = q.u;
+            pl[slot][2][r] = q.v;
+            pl[slot][3][r] = q.w;
+            pl[slot][4][r] = q.p;
+        }
+    };
+
+    // z-window of the own column: planes p-2 .. p+2 (index 0 .. 4)
+    double wr[5], wu[5], wv[5], ww[5], wp[5];
+    const int p0 = z0 >= 0 ? z0 - 1 : z0;  // warm-up plane for the first z-face flux
+    for (int z = p0 - 2; z <= p0 + 1; ++z) {
+        load_plane(z);
+        __syncthreads();
+        const int slot = (z + 6) % 3;
+        const int k = z - (p0 - 2) + 1;  // window index of plane z before the first shift
+        if (k >= 1) {
+            wr[k] = pl[slot][0][rc];
+            wu[k] = pl[slot][1][rc];
+            wv[k] = pl[slot][2][rc];
+            ww[k] = pl[slot][3][rc];
+            wp[k] = pl[slot][4][rc];
+        }
+        __syncthreads();
+    }
+    wr[0] = wu[0] = wv[0] = ww[0] = wp[0] = 0.0;
+
+    Face qz_hi_prev = {};
+    for (int p = p0; p < z1; ++p) {
+        load_plane(p + 2);
+        __syncthreads();
+        {  // shift the window and append plane p+2
+            const int slot = (p + 2 + 6) % 3;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                wr[k] = wr[k + 1];
+                wu[k] = wu[k + 1];
+                wv[k] = wv[k + 1];
+                ww[k] = ww[k + 1];
+                wp[k] = wp[k + 1];
+            }
+            wr[4] = pl[slot][0][rc];
+            wu[4] = pl[slot][1][rc];
+            wv[4] = pl[slot][2][rc];
+            ww[4] = pl[slot][3][rc];
+            wp[4] = pl[slot][4][rc];
+        }
+        const double ri = 1.0 / wr[2];  // as the cell's primitive conversion forms it
+        const double c = sound_ri(gamma, wp[2], ri);
+        // ------------------------------------------------ z trace
+        Face zh, zl;
+        trace_cell(wr, ww, wu, wv, wp, c, ri, 2, dtdz, zh, zl);
+        if (gx != 0.0) { zh.u = zh.u + h * gx; zl.u = zl.u + h * gx; }
+        if (gy != 0.0) { zh.v = zh.v + h * gy; zl.v = zl.v + h * gy; }
+        if (gz != 0.0) { zh.w = zh.w + h * gz; zl.w = zl.w + h * gz; }
+        const Flux F1z = hllc(qz_hi_prev, zl, 2, gamma, igm1);
+        qz_hi_prev = zh;
+        if (p < z0) {  // warm-up plane: only the z high-face state is needed
+            __syncthreads();
+            continue;
+        }
+        // ------------------------------------------------ x and y traces of plane p
+        const int slot = (p + 6) % 3;
+        Face xh, xl, yh, yl;
+        {
+            double rs[5], a1[5], a2[5], a3[5], ps[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const int r = rc + (m - 2);
+                rs[m] = pl[slot][0][r];
+                a1[m] = pl[slot][1][r];
+                a2[m] = pl[slot][2][r];
+                a3[m] = pl[slot][3][r];
+                ps[m] = pl[slot][4][r];
+            }
+            trace_cell(rs, a1, a2, a3, ps, c, ri, 0, dtdx, xh, xl);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const int r = rc + (m - 2) * RW;
+                rs[m] = pl[slot][0][r];
+                a1[m] = pl[slot][2][r];
+                a2[m] = pl[slot][1][r];
+                a3[m] = pl[slot][3][r];
+                ps[m] = pl[slot][4][r];
+            }
+            trace_cell(rs, a1, a2, a3, ps, c, ri, 1, dtdy, yh, yl);
+        }
+        if (gx != 0.0) {
+            xh.u = xh.u + h * gx; xl.u = xl.u + h * gx;
+            yh.u = yh.u + h * gx; yl.u = yl.u + h * gx;
+        }
+        if (gy != 0.0) {
+            xh.v = xh.v + h * gy; xl.v = xl.v + h * gy;
+            yh.v = yh.v + h * gy; yl.v = yl.v + h * gy;
+        }
+        if (gz != 0.0) {
+            xh.w = xh.w + h * gz; xl.w = xl.w + h * gz;
+            yh.w = yh.w + h * gz; yl.w = yl.w + h * gz;
+        }
+        putF(xq, 0, t, xh);
+        putF(xq, 5, t, yh);
+        __syncthreads();
+        const Flux F1x = hllc(getF(xq, 0, tL), xl, 0, gamma, igm1);
+        const Flux F1y = hllc(getF(xq, 5, tD), yl, 1, gamma, igm1);
+        if (inner) {
+            const long long c0 = cell(g, x, y, p);
+            ws.f(QHI(0, 0))[c0] = xh.r; ws.f(QHI(0, 1))[c0] = xh.u; ws.f(QHI(0, 2))[c0] = xh.v;
+            ws.f(QHI(0, 3))[c0] = xh.w; ws.f(QHI(0, 4))[c0] = xh.p;
+            ws.f(QLO(0, 0))[c0] = xl.r; ws.f(QLO(0, 1))[c0] = xl.u; ws.f(QLO(0, 2))[c0] = xl.v;
+            ws.f(QLO(0, 3))[c0] = xl.w; ws.f(QLO(0, 4))[c0] = xl.p;
+            ws.f(QHI(1, 0))[c0] = yh.r; ws.f(QHI(1, 1))[c0] = yh.u; ws.f(QHI(1, 2))[c0] = yh.v;
+            ws.f(QHI(1, 3))[c0] = yh.w; ws.f(QHI(1, 4))[c0] = yh.p;
+            ws.f(QLO(1, 0))[c0] = yl.r; ws.f(QLO(1, 1))[c0] = yl.u; ws.f(QLO(1, 2))[c0] = yl.v;
+            ws.f(QLO(1, 3))[c0] = yl.w; ws.f(QLO(1, 4))[c0] = yl.p;
+            ws.f(QHI(2, 0))[c0] = zh.r; ws.f(QHI(2, 1))[c0] = zh.u; ws.f(QHI(2, 2))[c0] = zh.v;
+            ws.f(QHI(2, 3))[c0] = zh.w; ws.f(QHI(2, 4))[c0] = zh.p;
+            ws.f(QLO(2, 0))[c0] = zl.r; ws.f(QLO(2, 1))[c0] = zl.u; ws.f(QLO(2, 2))[c0] = zl.v;
+            ws.f(QLO(2, 3))[c0] = zl.w; ws.f(QLO(2, 4))[c0] = zl.p;
+            if (x >= 0) store_flux(ws, F1F(0, 0), c0, F1x);
+            if (y >= 0) store_flux(ws, F1F(1, 0), c0, F1y);
+            if (p >= 0) store_flux(ws, F1F(2, 0), c0, F1z);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
