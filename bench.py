@@ -38,6 +38,37 @@ sys.path.insert(0, ROOT)
 # counts an FMA as two flops)
 PEAK_FP64_NOFMA = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
+# oracle stages computed by each kernel group of the library's advance
+KERNEL_STAGES = {"trace_flux1": ["prim", "trace", "flux1"],
+                 "corner_final_update": ["corner_flux2", "final_flux3", "update"]}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rt512_traffic.json")
+KERNEL_SYMBOL = {"trace_flux1": "k_trace_fused", "corner_final_update": "k_flux_fused"}
+
+
+def source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2007_05218_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile,
+    if it was taken on the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(KERNEL_SYMBOL.get(kernel, kernel))
+    if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def log(*a):
@@ -50,7 +81,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workloads", default="rt512,kh256,level,serve",
-                    help="comma list of rt512, kh256, level, serve")
+                    help="comma list of rt512, kh256, level, serve, copy (a plain 2 GiB "
+                         "device copy, the reference for HBM traffic counters)")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-warmup", type=int, default=20)
     ap.add_argument("--level-steps", type=int, default=5)
@@ -84,10 +116,8 @@ def time_box(hydro, torch, U, box, prm, steps, warmup):
     return ms, wall, timer, err
 
 
-def time_level(hydro, torch, inputs, steps, warmup):
-    states, boxes, prm = inputs.level(nboxes=512, seed=2)
-    cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in boxes)
-    lev = hydro.Level(states, boxes, prm, shared_dt=True)
+def _time_level_once(hydro, torch, states, boxes, prm, steps, warmup, table=None):
+    lev = hydro.Level(states, boxes, prm, shared_dt=True, autotune_json=table)
     for _ in range(warmup):
         lev.step()
     torch.cuda.synchronize()
@@ -97,9 +127,22 @@ def time_level(hydro, torch, inputs, steps, warmup):
         lev.step()
     e1.record()
     torch.cuda.synchronize()
-    ms_batched = e0.elapsed_time(e1)
+    ms = e0.elapsed_time(e1)
     del lev
     torch.cuda.empty_cache()
+    return ms
+
+
+def time_level(hydro, torch, inputs, steps, warmup):
+    from paper_2007_05218_amd import autotune
+    states, boxes, prm = inputs.level(nboxes=512, seed=2)
+    cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in boxes)
+    t0 = time.perf_counter()
+    table, _ = autotune.tune(boxes, prm, log=log)
+    tune_s = time.perf_counter() - t0
+    js = autotune.table_json(table)
+    ms_default = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup)
+    ms_batched = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup, js)
     # the same boxes, one library call per box and stage (one stream)
     Us = [torch.tensor(u, device="cuda") for u in states]
     Uns = [torch.empty_like(u) for u in Us]
@@ -127,10 +170,14 @@ def time_level(hydro, torch, inputs, steps, warmup):
     ms_per_box = e0.elapsed_time(e1)
     del Us, Uns, ws
     torch.cuda.empty_cache()
-    return {"workload": "level512", "boxes": len(boxes), "cells": cells, "steps": steps,
+    return {"workload": "level512: 512 periodic boxes, sides from {16,32,64} per axis, "
+                        "smooth random fields, dx=1/64, shared dt, seed 2",
+            "boxes": len(boxes), "cells": cells, "steps": steps,
             "batched_cu_per_s": cells * steps / (ms_batched * 1e-3),
+            "batched_untuned_cu_per_s": cells * steps / (ms_default * 1e-3),
             "per_box_cu_per_s": cells * steps / (ms_per_box * 1e-3),
-            "batched_ms_per_step": ms_batched / steps, "per_box_ms_per_step": ms_per_box / steps}
+            "batched_ms_per_step": ms_batched / steps, "per_box_ms_per_step": ms_per_box / steps,
+            "autotune_s": tune_s, "tile_table": table}
 
 
 def time_serving(inputs, nreq, warm, seed=3):
@@ -171,7 +218,8 @@ def cpu_baseline(inputs, U, box, prm, seconds):
     U = U.copy()
     orc.fill_ghosts(U, ob)
     dt = orc.estimate_dt(U, ob, op)
-    ops = orc.opcount_cell(U, ob, op, dt, N=10)
+    ops = {k: orc.opcount_cell(U, ob, op, dt, N=16, stage=v) for k, v in KERNEL_STAGES.items()}
+    ops["step"] = orc.opcount_cell(U, ob, op, dt, N=16)
     n = box["n"]
     Unew = U.copy()
     slab = 4
@@ -206,6 +254,17 @@ def main():
     work = [w.strip() for w in args.workloads.split(",") if w.strip()]
     rank = int(os.environ.get("RANK", "0"))
 
+    if "copy" in work:
+        a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.neg(a, out=b)  # an elementwise kernel: 2 GiB read, 2 GiB written
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
+        log("copy: 2 GiB read + 2 GiB written")
     log("building RT 512^3 input")
     U, box, prm = inputs.rt(512, seed=4)
     ncell = box["n"][0] * box["n"][1] * box["n"][2]
@@ -221,23 +280,28 @@ def main():
     if rank == 0 and not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cpu, ops = cpu_baseline(inputs, U, box, prm, args.cpu_seconds)
-        log("cpu baseline:", json.dumps(cpu), "ops/cell:", json.dumps(ops))
-    flops_cell = (ops["add"] + ops["mul"] + ops["div"] + ops["sqrt"]) if ops else None
+        log("cpu baseline:", json.dumps(cpu), "ops/cell-update:", json.dumps(ops))
+    def flops(o):
+        return o["add"] + o["mul"] + o["div"] + o["sqrt"]
 
-    # dominant kernel group and its roofline
-    dom = max((k for k in stage_ms if k not in ("fill", "dt")), key=lambda k: stage_ms[k])
-    adv_ms = sum(v for k, v in stage_ms.items() if k not in ("fill", "dt"))
+    # dominant kernel group and its roofline: algorithmic FP64 operations of
+    # the oracle stages it computes, per cell-update, x cells / its device time
+    adv = {k: v for k, v in stage_ms.items() if k in KERNEL_STAGES}
+    dom = max(adv, key=adv.get)
     roof = None
-    if flops_cell:
-        # the whole advance's algorithmic flops credited to the advance's time;
-        # the dominant group's share is reported beside it
-        ach = flops_cell * ncell / (adv_ms * 1e-3)
+    if ops:
+        ach = flops(ops[dom]) * ncell / (stage_ms[dom] * 1e-3)
+        traffic = measured_traffic(dom)
         roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_NOFMA / 1e12,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_NOFMA, "traffic": None,
-                "kernel": "advance (all stages)", "dominant_stage": dom,
-                "dominant_stage_ms": stage_ms[dom], "advance_ms": adv_ms,
-                "flops_per_cell_update": flops_cell,
-                "hbm_frac_on_80B_per_cu": 80.0 * ncell / (adv_ms * 1e-3) / HBM_PEAK}
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_NOFMA, "traffic": traffic,
+                "kernel": KERNEL_SYMBOL[dom], "kernel_ms": stage_ms[dom],
+                "flops_per_cell_update": flops(ops[dom]),
+                "step_flops_per_cell_update": flops(ops["step"]),
+                "step_frac": flops(ops["step"]) * ncell / (ms / args.steps * 1e-3) / PEAK_FP64_NOFMA,
+                "other_kernels": {KERNEL_SYMBOL[k]: {"ms": stage_ms[k],
+                                                     "frac": flops(ops[k]) * ncell / (stage_ms[k] * 1e-3) / PEAK_FP64_NOFMA}
+                                  for k in adv if k != dom},
+                "hbm_frac_80B_per_cu": 80.0 * value / HBM_PEAK}
 
     also = {}
     if "kh256" in work:

@@ -33,6 +33,12 @@
 #include <omp.h>
 #endif
 
+/* hook for the operation-counting build (oracle/opcount.cpp): marks the end
+ * of stage k of orc_advance_region; a no-op here */
+#ifndef ORC_STAGE_MARK
+#define ORC_STAGE_MARK(k) ((void)0)
+#endif
+
 #define C6 (1.0 / 6.0)
 #define C23 (2.0 / 3.0)
 
@@ -178,10 +184,10 @@ void orc_prim_of_cons(const double U[5], double gamma, double q[5])
     for (int v = 0; v < 5; ++v) q[v] = t[v];
 }
 
-static void cons_of(const double q[5], double gm1, double U[5])
+/* conserved variables of a primitive state; igm1 = 1/(gamma-1) */
+static void cons_of(const double q[5], double igm1, double U[5])
 {
     double rho = q[0], u = q[1], v = q[2], w = q[3], p = q[4];
-    double igm1 = 1.0 / gm1;
     U[0] = rho;
     U[1] = rho * u;
     U[2] = rho * v;
@@ -191,7 +197,7 @@ static void cons_of(const double q[5], double gm1, double U[5])
 
 void orc_cons_of_prim(const double q[5], double gamma, double U[5])
 {
-    cons_of(q, gamma - 1.0, U);
+    cons_of(q, 1.0 / (gamma - 1.0), U);
 }
 
 /* ------------------------------------------------------------------ */
@@ -271,17 +277,22 @@ void orc_ppm_parabola(const double a5[5], double out[2])
 }
 
 /* average of the parabola over the part of the cell swept by a wave of speed
- * lam in time dt (s = |lam| dt/dx), next to the high face (Ip, lam > 0) and
- * next to the low face (Im, lam < 0); waves moving away give the face value */
-static void ppm_edge(double ac, double aL, double aR, double lam, double dtdx,
-                     double *Ip, double *Im)
+ * lam in time dt (s = |lam| dt/dx), next to the high face (lam > 0) or next
+ * to the low face (lam < 0); a wave moving away leaves the face value */
+static double edge_hi(double ac, double aL, double aR, double lam, double dtdx)
 {
     double dA = aR - aL;
     double a6 = 6.0 * (ac - 0.5 * (aL + aR));
-    double sp = (lam > 0.0 ? lam : 0.0) * dtdx;
-    double sm = (lam < 0.0 ? -lam : 0.0) * dtdx;
-    *Ip = aR - (0.5 * sp) * (dA - (1.0 - C23 * sp) * a6);
-    *Im = aL + (0.5 * sm) * (dA + (1.0 - C23 * sm) * a6);
+    double s = (lam > 0.0 ? lam : 0.0) * dtdx;
+    return aR - (0.5 * s) * (dA - (1.0 - C23 * s) * a6);
+}
+
+static double edge_lo(double ac, double aL, double aR, double lam, double dtdx)
+{
+    double dA = aR - aL;
+    double a6 = 6.0 * (ac - 0.5 * (aL + aR));
+    double s = (lam < 0.0 ? -lam : 0.0) * dtdx;
+    return aL + (0.5 * s) * (dA + (1.0 - C23 * s) * a6);
 }
 
 void orc_ppm_integrals(const double a5[5], double lam, double dtdx, double *Ip,
@@ -289,7 +300,8 @@ void orc_ppm_integrals(const double a5[5], double lam, double dtdx, double *Ip,
 {
     double aL, aR;
     ppm_faces(a5, &aL, &aR);
-    ppm_edge(a5[2], aL, aR, lam, dtdx, Ip, Im);
+    *Ip = edge_hi(a5[2], aL, aR, lam, dtdx);
+    *Im = edge_lo(a5[2], aL, aR, lam, dtdx);
 }
 
 /* ------------------------------------------------------------------ */
@@ -322,16 +334,16 @@ static void trace_cell(const double q[5][5], double c, int d, double dtdx,
     const double un = q[2][1 + d];
     const double lam[3] = {un - c, un, un + c};
 
-    /* Ip[v][nu], Im[v][nu] for v in trace order, nu = -,0,+ */
-    double Ip[5][3], Im[5][3];
+    /* limited parabola of each variable (trace order) */
+    double ac[5], aL[5], aR[5];
     for (int v = 0; v < 5; ++v) {
         double a[5];
         for (int m = 0; m < 5; ++m) a[m] = q[m][var[v]];
-        double aL, aR;
-        ppm_faces(a, &aL, &aR);
-        for (int nu = 0; nu < 3; ++nu)
-            ppm_edge(a[2], aL, aR, lam[nu], dtdx, &Ip[v][nu], &Im[v][nu]);
+        ppm_faces(a, &aL[v], &aR[v]);
+        ac[v] = a[2];
     }
+#define IP(v, nu) edge_hi(ac[v], aL[v], aR[v], lam[nu], dtdx)
+#define IM(v, nu) edge_lo(ac[v], aL[v], aR[v], lam[nu], dtdx)
 
     const double rc = rho * c;
     const double cs2 = c * c;
@@ -341,36 +353,38 @@ static void trace_cell(const double q[5][5], double c, int d, double dtdx,
 
     /* high face: reference = + wave */
     {
-        double r_rho = Ip[0][2], r_un = Ip[1][2], r_p = Ip[4][2];
-        double dum = r_un - Ip[1][0];
-        double dpm = r_p - Ip[4][0];
-        double drz = r_rho - Ip[0][1];
-        double dpz = r_p - Ip[4][1];
+        double r_rho = IP(0, 2), r_un = IP(1, 2), r_p = IP(4, 2);
+        double dum = r_un - IP(1, 0);
+        double dpm = r_p - IP(4, 0);
+        double drz = r_rho - IP(0, 1);
+        double dpz = r_p - IP(4, 1);
         double am = lam[0] > 0.0 ? (0.5 * (dpm - rc * dum)) * ics2 : 0.0;
         double az = lam[1] > 0.0 ? drz - dpz * ics2 : 0.0;
         f[0] = r_rho - (am + az);
         f[1] = r_un + cor * am;
-        f[2] = lam[1] > 0.0 ? Ip[2][1] : Ip[2][2];
-        f[3] = lam[1] > 0.0 ? Ip[3][1] : Ip[3][2];
+        f[2] = lam[1] > 0.0 ? IP(2, 1) : IP(2, 2);
+        f[3] = lam[1] > 0.0 ? IP(3, 1) : IP(3, 2);
         f[4] = r_p - cs2 * am;
         for (int v = 0; v < 5; ++v) qhi[var[v]] = f[v];
     }
     /* low face: reference = - wave */
     {
-        double r_rho = Im[0][0], r_un = Im[1][0], r_p = Im[4][0];
-        double dup = r_un - Im[1][2];
-        double dpp = r_p - Im[4][2];
-        double drz = r_rho - Im[0][1];
-        double dpz = r_p - Im[4][1];
+        double r_rho = IM(0, 0), r_un = IM(1, 0), r_p = IM(4, 0);
+        double dup = r_un - IM(1, 2);
+        double dpp = r_p - IM(4, 2);
+        double drz = r_rho - IM(0, 1);
+        double dpz = r_p - IM(4, 1);
         double ap = lam[2] < 0.0 ? (0.5 * (dpp + rc * dup)) * ics2 : 0.0;
         double az = lam[1] < 0.0 ? drz - dpz * ics2 : 0.0;
         f[0] = r_rho - (az + ap);
         f[1] = r_un - cor * ap;
-        f[2] = lam[1] < 0.0 ? Im[2][1] : Im[2][0];
-        f[3] = lam[1] < 0.0 ? Im[3][1] : Im[3][0];
+        f[2] = lam[1] < 0.0 ? IM(2, 1) : IM(2, 0);
+        f[3] = lam[1] < 0.0 ? IM(3, 1) : IM(3, 0);
         f[4] = r_p - cs2 * ap;
         for (int v = 0; v < 5; ++v) qlo[var[v]] = f[v];
     }
+#undef IP
+#undef IM
 }
 
 void orc_trace(const double q5[5][5], int d, double gamma, double dtdx,
@@ -416,18 +430,19 @@ static void star_flux(const double q[5], double E, int d, double SK, double Ss,
     for (int v = 0; v < 5; ++v) F[v] = FK[v] + SK * (Us[v] - UK[v]);
 }
 
-static double total_energy(const double q[5], double gm1)
+static double total_energy(const double q[5], double igm1)
 {
-    return q[4] * (1.0 / gm1) + (0.5 * q[0]) * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
+    return q[4] * igm1 + (0.5 * q[0]) * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
 }
 
+/* igm1 = 1/(gamma-1) */
 static void hllc(const double qL[5], const double qR[5], int d, double gamma,
-                 double gm1, double F[5])
+                 double igm1, double F[5])
 {
     double rL = qL[0], uL = qL[1 + d], pL = qL[4];
     double rR = qR[0], uR = qR[1 + d], pR = qR[4];
-    double EL = total_energy(qL, gm1);
-    double ER = total_energy(qR, gm1);
+    double EL = total_energy(qL, igm1);
+    double ER = total_energy(qR, igm1);
     double cL = sqrt((gamma * pL) / rL);
     double cR = sqrt((gamma * pR) / rR);
     /* Davis (1988) wave-speed bounds */
@@ -449,7 +464,7 @@ static void hllc(const double qL[5], const double qR[5], int d, double gamma,
 void orc_hllc(const double qL[5], const double qR[5], int d, double gamma,
               double F[5])
 {
-    hllc(qL, qR, d, gamma, gamma - 1.0, F);
+    hllc(qL, qR, d, gamma, 1.0 / (gamma - 1.0), F);
 }
 
 /* ------------------------------------------------------------------ */
@@ -534,7 +549,7 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
     extents(b, s);
     const long long cs = s[0] * s[1] * s[2];
     const int ng = b->ng;
-    const double gamma = pr->gamma, gm1 = gamma - 1.0;
+    const double gamma = pr->gamma, gm1 = gamma - 1.0, igm1 = 1.0 / gm1;
     int err = 0;
     int rc = 0;
 
@@ -562,6 +577,7 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
         for (int c = 0; c < 5; ++c) Uc[c] = U[c * cs + o];
         prim_c(Uc, gamma, gm1, fat(&prim, p));
     })
+    ORC_STAGE_MARK(1);
 
     /* A3 + A4: traced states at both faces of every cell, each direction,
      * on the cells one beyond the output region; then the half-step
@@ -591,6 +607,8 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
         })
     }
 
+    ORC_STAGE_MARK(4);
+
     /* A5: round-1 fluxes at d-faces; face f lies between cells f-1 and f */
     for (int d = 0; d < 3; ++d) {
         int flo[3], fhi[3];
@@ -602,9 +620,11 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
         FOR_REGION(flo, fhi, p, {
             int l[3] = {p[0], p[1], p[2]};
             l[d] -= 1;
-            hllc(fat(&qhi[d], l), fat(&qlo[d], p), d, gamma, gm1, fat(&F1[d], p));
+            hllc(fat(&qhi[d], l), fat(&qlo[d], p), d, gamma, igm1, fat(&F1[d], p));
         })
     }
+
+    ORC_STAGE_MARK(5);
 
     /* A6: corner coupling.  F2[t][s] is the flux through t-faces of the
      * states traced along t and corrected by dt/3 of the round-1 s-flux
@@ -633,14 +653,16 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
                     const double *Flo = fat(&F1[sd], c), *Fhi = fat(&F1[sd], cu);
                     const double *q = side ? fat(&qlo[t], c) : fat(&qhi[t], c);
                     double Uq[5], V[5];
-                    cons_of(q, gm1, Uq);
+                    cons_of(q, igm1, Uq);
                     for (int v = 0; v < 5; ++v)
                         V[v] = Uq[v] - fac * (Fhi[v] - Flo[v]);
                     err |= accept_state(V, q, gm1, qc[side]);
                 }
-                hllc(qc[0], qc[1], t, gamma, gm1, fat(&F2[t][sd], p));
+                hllc(qc[0], qc[1], t, gamma, igm1, fat(&F2[t][sd], p));
             })
         }
+
+    ORC_STAGE_MARK(6);
 
     /* A7: final states, corrected by dt/2 of both round-2 transverse flux
      * differences, and the round-3 fluxes at d-faces of the output region */
@@ -668,14 +690,16 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
                 const double *B0 = fat(&F2[t2][t1], c), *B1 = fat(&F2[t2][t1], c2);
                 const double *q = side ? fat(&qlo[d], c) : fat(&qhi[d], c);
                 double Uq[5], V[5];
-                cons_of(q, gm1, Uq);
+                cons_of(q, igm1, Uq);
                 for (int v = 0; v < 5; ++v)
                     V[v] = (Uq[v] - f1 * (A1[v] - A0[v])) - f2 * (B1[v] - B0[v]);
                 err |= accept_state(V, q, gm1, qf[side]);
             }
-            hllc(qf[0], qf[1], d, gamma, gm1, fat(&F3[d], p));
+            hllc(qf[0], qf[1], d, gamma, igm1, fat(&F3[d], p));
         })
     }
+
+    ORC_STAGE_MARK(7);
 
     /* A8: conservative update and time-centred gravity source */
     {
@@ -710,6 +734,8 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
             if (qn[4] <= 0.0) err |= ORC_ERR_P;
         })
     }
+
+    ORC_STAGE_MARK(8);
 
 done:
     free(prim.v);

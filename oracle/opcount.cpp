@@ -17,6 +17,10 @@ struct OpCounts {
     long long add, mul, div, sqrt_, cmp;
 };
 static OpCounts g_ops;
+static OpCounts g_mark[9];  // counts at the end of each marked stage
+
+static void stage_mark(int k) { g_mark[k] = g_ops; }
+#define ORC_STAGE_MARK(k) stage_mark(k)
 
 struct D {
     double v;
@@ -47,30 +51,35 @@ static inline bool operator!(D a) { return !a.v; }
 
 extern "C" {
 
-/* ops[5] = add, mul, div, sqrt, cmp of one cell-update, interior cells of a
- * box with uniform-ish data from U (ghosts filled), region sizes N and N+1. */
-int orc_opcount_cell(const double *U, const orc_box *b, const orc_params *p,
-                     double dt, int N, double ops[5])
+/* Operation counts of one orc_advance_region call on the output region
+ * [0,N)^3 of the box (U with ghosts filled): ops[k] = (add, mul, div, sqrt,
+ * cmp) spent in the stages that end at mark k (1: primitives, 4: PPM +
+ * tracing, 5: round-1 fluxes, 6: corner coupling + round 2, 7: final states
+ * + round 3, 8: update); rows 0, 2, 3 are unused. */
+int orc_opcount_region(const double *U, const orc_box *b, const orc_params *p, double dt,
+                       int N, double ops[9][5])
 {
     double *Un = (double *)malloc(sizeof(double) * orc_state_elems(b));
     if (!Un) return -2;
     int err = 0;
     int lo[3] = {0, 0, 0};
-    int hiA[3] = {N, N, N}, hiB[3] = {N + 1, N, N};
-    OpCounts a, c;
+    int hi[3] = {N, N, N};
     memset(&g_ops, 0, sizeof g_ops);
-    int rc = orc_advance_region((const D *)U, (D *)Un, b, p, D(dt), lo, hiA, &err);
-    a = g_ops;
-    memset(&g_ops, 0, sizeof g_ops);
-    rc |= orc_advance_region((const D *)U, (D *)Un, b, p, D(dt), lo, hiB, &err);
-    c = g_ops;
+    memset(g_mark, 0, sizeof g_mark);
+    int rc = orc_advance_region((const D *)U, (D *)Un, b, p, D(dt), lo, hi, &err);
     free(Un);
-    double nn = (double)N * N;
-    ops[0] = (c.add - a.add) / nn;
-    ops[1] = (c.mul - a.mul) / nn;
-    ops[2] = (c.div - a.div) / nn;
-    ops[3] = (c.sqrt_ - a.sqrt_) / nn;
-    ops[4] = (c.cmp - a.cmp) / nn;
+    OpCounts prev = {0, 0, 0, 0, 0};
+    for (int k = 0; k < 9; ++k) {
+        for (int v = 0; v < 5; ++v) ops[k][v] = 0.0;
+        if (k != 1 && k < 4) continue;
+        const OpCounts &m = g_mark[k];
+        ops[k][0] = (double)(m.add - prev.add);
+        ops[k][1] = (double)(m.mul - prev.mul);
+        ops[k][2] = (double)(m.div - prev.div);
+        ops[k][3] = (double)(m.sqrt_ - prev.sqrt_);
+        ops[k][4] = (double)(m.cmp - prev.cmp);
+        prev = m;
+    }
     return rc;
 }
 }

@@ -194,19 +194,43 @@ def num_threads():
     return lib().orc_num_threads()
 
 
-def opcount_cell(U, box, prm, dt, N=8):
-    """Operations of one cell-update (add, mul, div, sqrt, cmp) counted by the
-    operation-counting build of the oracle on the data of U (ghosts filled)."""
+# stage -> (mark index, work units of the stage per cell-update of an
+# unbounded box: 1 primitive conversion, 3 traced cells (one per direction),
+# 3 round-1 faces, 6 round-2 faces, 3 round-3 faces, 1 update)
+STAGES = {"prim": (1, 1), "trace": (4, 3), "flux1": (5, 3), "corner_flux2": (6, 6),
+          "final_flux3": (7, 3), "update": (8, 1)}
+
+
+def _stage_units(N, stage):
+    """Work units the oracle's stage regions hold for an N^3 output region."""
+    n1, n2, n6 = N + 1, N + 2, N + 6
+    return {"prim": n6 ** 3, "trace": 3 * n2 ** 3, "flux1": 3 * n1 * n2 * n2,
+            "corner_flux2": 6 * n1 * N * n2, "final_flux3": 3 * n1 * N * N,
+            "update": N ** 3}[stage]
+
+
+def opcount_cell(U, box, prm, dt, N=16, stage=None):
+    """Algorithmic operations (add, mul, div, sqrt, cmp) of one cell-update,
+    counted by the operation-counting build of the oracle on the data of U
+    (ghosts filled): each stage's average cost per work unit over an N^3
+    output region, times its work units per cell of an unbounded box (no
+    halo recomputation).  ``stage``: None for the whole step, a stage name or
+    a list of names (see STAGES)."""
     path = _build.OPC_LIB
     if not os.path.exists(path):
         _build.build()
     L = C.CDLL(path)
-    L.orc_opcount_cell.argtypes = [C.POINTER(C.c_double), C.POINTER(OrcBox),
-                                   C.POINTER(OrcParams), C.c_double, C.c_int,
-                                   C.POINTER(C.c_double)]
-    ops = np.zeros(5)
-    rc = L.orc_opcount_cell(_dp(np.ascontiguousarray(U)), C.byref(box), C.byref(prm), dt, N,
-                            _dp(ops))
+    L.orc_opcount_region.argtypes = [C.POINTER(C.c_double), C.POINTER(OrcBox),
+                                     C.POINTER(OrcParams), C.c_double, C.c_int,
+                                     C.POINTER(C.c_double)]
+    ops = np.zeros((9, 5))
+    rc = L.orc_opcount_region(_dp(np.ascontiguousarray(U)), C.byref(box), C.byref(prm), dt, N,
+                              _dp(ops))
     if rc != 0:
-        raise RuntimeError("orc_opcount_cell failed")
-    return dict(zip(("add", "mul", "div", "sqrt", "cmp"), ops.tolist()))
+        raise RuntimeError("orc_opcount_region failed")
+    names = list(STAGES) if stage is None else ([stage] if isinstance(stage, str) else stage)
+    tot = np.zeros(5)
+    for s in names:
+        k, per_cell = STAGES[s]
+        tot += ops[k] / _stage_units(N, s) * per_cell
+    return dict(zip(("add", "mul", "div", "sqrt", "cmp"), tot.tolist()))

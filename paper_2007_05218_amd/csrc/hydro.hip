@@ -459,6 +459,68 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
     return launch_status();
 }
 
+// ---------------------------------------------------------------- tile table
+
+// A tuned tile table: a flat JSON object mapping a box shape "NXxNYxNZ" to a
+// pair [tbx, tzs] (tile width in columns, z-segment length), e.g.
+//   {"16x32x64": [16, 32], "64x64x64": [32, 16]}
+// as written by the package's autotuner.  Shapes not listed keep the
+// built-in choice.  Returns false on a syntax error or an invalid tile.
+struct TileRule {
+    int n[3];
+    int tbx, tzs;
+};
+
+bool parse_tiles(const char *js, std::vector<TileRule> &out)
+{
+    const char *c = js;
+    auto ws = [&]() { while (*c == ' ' || *c == '\n' || *c == '\t' || *c == '\r') ++c; };
+    auto num = [&](int &v) {
+        ws();
+        if (*c < '0' || *c > '9') return false;
+        long long a = 0;
+        while (*c >= '0' && *c <= '9') {
+            a = a * 10 + (*c - '0');
+            if (a > (1 << 30)) return false;
+            ++c;
+        }
+        v = (int)a;
+        return true;
+    };
+    ws();
+    if (*c++ != '{') return false;
+    ws();
+    if (*c == '}') return true;
+    for (;;) {
+        TileRule r;
+        ws();
+        if (*c++ != '"') return false;
+        if (!num(r.n[0]) || *c++ != 'x' || !num(r.n[1]) || *c++ != 'x' || !num(r.n[2]))
+            return false;
+        if (*c++ != '"') return false;
+        ws();
+        if (*c++ != ':') return false;
+        ws();
+        if (*c++ != '[') return false;
+        if (!num(r.tbx)) return false;
+        ws();
+        if (*c++ != ',') return false;
+        if (!num(r.tzs)) return false;
+        ws();
+        if (*c++ != ']') return false;
+        if (!tiles_valid(r.tbx, r.tzs)) return false;
+        out.push_back(r);
+        ws();
+        if (*c == ',') {
+            ++c;
+            continue;
+        }
+        if (*c++ != '}') return false;
+        ws();
+        return *c == 0;
+    }
+}
+
 // ---------------------------------------------------------------- plans
 
 struct Plan {
@@ -548,9 +610,10 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
 hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,
                                void **plan_out)
 {
-    (void)autotune_json;
     if (!boxes || nb < 1 || !plan_out) return HYDRO_EINVAL;
     *plan_out = nullptr;
+    std::vector<TileRule> rules;
+    if (autotune_json && !parse_tiles(autotune_json, rules)) return HYDRO_EINVAL;
     Plan *P = new (std::nothrow) Plan();
     if (!P) return HYDRO_EINVAL;
     P->nb = nb;
@@ -564,6 +627,11 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
             return HYDRO_EINVAL;
         }
         Geo g = make_geo(&boxes[b]);
+        for (const TileRule &r : rules)
+            if (r.n[0] == g.n[0] && r.n[1] == g.n[1] && r.n[2] == g.n[2]) {
+                g.tbx = r.tbx;
+                g.tzs = r.tzs;
+            }
         P->geos.push_back(g);
         wsoff[b] = (long long)(P->ws_bytes / sizeof(double));
         P->ws_bytes += box_ws_bytes(g);

@@ -106,3 +106,21 @@ def test_status_strings():
     L = hydro.lib()
     for s in range(4):
         assert L.hydro_status_string(s).startswith(b"HYDRO_")
+
+
+@pytest.mark.parametrize("js", ['{"16x16x16": [12, 8]}', '{"16x16x16": [16, 0]}', '{16x16x16: [16, 8]}',
+                                '{"16x16": [16, 8]}', '["16x16x16"]', '{"16x16x16": [16, 8]} x'])
+def test_plan_rejects_bad_tile_tables(js):
+    # the table is parsed before any device allocation, so this needs no GPU
+    L = hydro.lib()
+    arr = (hydro.HydroBox * 1)(hydro.make_box(inputs.box_desc((16, 16, 16))))
+    h = C.c_void_p()
+    assert L.hydro_plan_create(arr, 1, js.encode(), C.byref(h)) == hydro.HYDRO_EINVAL
+
+
+def test_autotune_table_format():
+    from paper_2007_05218_amd import autotune
+    js = autotune.table_json({"16x32x64": (16, 32), "64x64x64": (32, 64)})
+    assert js == '{"16x32x64": [16, 32], "64x64x64": [32, 64]}'
+    c = autotune.candidates((16, 32, 64))
+    assert (8, 64) in c and (32, 8) in c and all(t[0] in (8, 16, 32) for t in c)

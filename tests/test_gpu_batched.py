@@ -90,3 +90,34 @@ def test_full_level_batched_equals_per_box(gpu, orc):
         orc.advance_box(U, Un, ob, op, dmin)
         e, bw = compare(inputs.valid(gs[b], boxes[b]), inputs.valid(Un, boxes[b]))
         assert e <= TOL and bw == 1.0
+
+
+def test_tile_shapes_do_not_change_results(gpu):
+    # every cell's arithmetic is independent of the tile it is computed in
+    import torch
+    from paper_2007_05218_amd import autotune
+    states, boxes, prm = inputs.level(nboxes=12, seed=8)
+    shapes = {tuple(b["n"]) for b in boxes}
+    res = []
+    for tb in [(8, 8), (16, 64), (32, 16)]:
+        table = {autotune.shape_key(n): tb for n in shapes}
+        lev = gpu.Level(states, boxes, prm, shared_dt=True,
+                        autotune_json=autotune.table_json(table))
+        lev.run(3)
+        torch.cuda.synchronize()
+        res.append((lev.states(), int(lev.err.item())))
+    for other, err in res[1:]:
+        assert err == res[0][1]
+        for a, b, box in zip(res[0][0], other, boxes):
+            assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box))
+
+
+def test_autotuner_runs(gpu):
+    from paper_2007_05218_amd import autotune
+    boxes = [inputs.box_desc((16, 32, 16)), inputs.box_desc((32, 16, 64))]
+    table, timings = autotune.tune(boxes, max_boxes_per_class=4, min_cells_per_class=1,
+                                   reps=1)
+    assert set(table) == {"16x32x16", "32x16x64"}
+    for k, (tbx, tzs) in table.items():
+        assert tbx in (8, 16, 32) and tzs >= 1
+    gpu.Plan(boxes, autotune.table_json(table)).close()
