@@ -69,7 +69,9 @@ enum {
                                 the uncorrected state was used (informational)       */
 };
 
-/* A box (Sec. II "Box"/"Fab"): 64 bytes, 8-byte aligned. */
+/* A box (Sec. II "Box"/"Fab"): 64 bytes, 8-byte aligned.  One component
+ * (with ghosts) must stay below 2^28 doubles (2 GiB), e.g. up to 636^3 valid
+ * cells with 4 ghost layers; larger domains are split into boxes. */
 typedef struct hydro_box {
     int32_t n[3];     /* valid cells per axis, >= 1; >= ng on periodic/reflect axes */
     int32_t ng;       /* ghost layers per side, 3 <= ng <= 8 (the stencil reads 3)  */

@@ -443,8 +443,8 @@ static void hllc(const double qL[5], const double qR[5], int d, double gamma,
     double rR = qR[0], uR = qR[1 + d], pR = qR[4];
     double EL = total_energy(qL, igm1);
     double ER = total_energy(qR, igm1);
-    double cL = sqrt((gamma * pL) / rL);
-    double cR = sqrt((gamma * pR) / rR);
+    double cL = sqrt((gamma * pL) * (1.0 / rL));
+    double cR = sqrt((gamma * pR) * (1.0 / rR));
     /* Davis (1988) wave-speed bounds */
     double SL = mn(uL - cL, uR - cR);
     double SR = mx(uL + cL, uR + cR);

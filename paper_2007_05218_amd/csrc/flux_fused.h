@@ -28,7 +28,7 @@ namespace {
 constexpr int kFT = 256;  // threads of a fused-flux block
 
 struct XBuf {
-    double v[10][kFT];
+    double v[12][kFT];
 };
 
 __device__ __forceinline__ void put5(double (*b)[kFT], int k0, int t, double a0, double a1,
@@ -40,9 +40,11 @@ __device__ __forceinline__ void put5(double (*b)[kFT], int k0, int t, double a0,
     b[k0 + 3][t] = a3;
     b[k0 + 4][t] = a4;
 }
+// states are exchanged with their 1/rho (6 slots from k0)
 __device__ __forceinline__ void putF(double (*b)[kFT], int k0, int t, const Face &f)
 {
     put5(b, k0, t, f.r, f.u, f.v, f.w, f.p);
+    b[k0 + 5][t] = f.ri;
 }
 __device__ __forceinline__ void putX(double (*b)[kFT], int k0, int t, const Flux &f)
 {
@@ -56,6 +58,7 @@ __device__ __forceinline__ Face getF(double (*b)[kFT], int k0, int t)
     f.v = b[k0 + 2][t];
     f.w = b[k0 + 3][t];
     f.p = b[k0 + 4][t];
+    f.ri = b[k0 + 5][t];
     return f;
 }
 __device__ __forceinline__ Flux getX(double (*b)[kFT], int k0, int t)
@@ -81,14 +84,33 @@ __device__ __forceinline__ Flux fdiff(const Flux &hi, const Flux &lo)
     return d;
 }
 
-__device__ __forceinline__ Flux load_flux(const WS &ws, int base, long long o)
+// loads at a 32-bit byte offset from a uniform field base (one component of
+// a box is below 2 GiB), so the address is a scalar base plus one VGPR
+__device__ __forceinline__ double ldb(const double *f, unsigned bo)
+{
+    return *(const double *)((const char *)f + bo);
+}
+
+__device__ __forceinline__ Face load_face_b(const WS &ws, int base, unsigned bo)
+{
+    Face f;
+    f.r = ldb(ws.f(base + 0), bo);
+    f.u = ldb(ws.f(base + 1), bo);
+    f.v = ldb(ws.f(base + 2), bo);
+    f.w = ldb(ws.f(base + 3), bo);
+    f.p = ldb(ws.f(base + 4), bo);
+    f.ri = 0.0;
+    return f;
+}
+
+__device__ __forceinline__ Flux load_flux_b(const WS &ws, int base, unsigned bo)
 {
     Flux f;
-    f.m = ws.f(base + 0)[o];
-    f.mu = ws.f(base + 1)[o];
-    f.mv = ws.f(base + 2)[o];
-    f.mw = ws.f(base + 3)[o];
-    f.e = ws.f(base + 4)[o];
+    f.m = ldb(ws.f(base + 0), bo);
+    f.mu = ldb(ws.f(base + 1), bo);
+    f.mv = ldb(ws.f(base + 2), bo);
+    f.mw = ldb(ws.f(base + 3), bo);
+    f.e = ldb(ws.f(base + 4), bo);
     return f;
 }
 
@@ -195,7 +217,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     const double fx2 = dt / (2.0 * g.dx[0]), fy2 = dt / (2.0 * g.dx[1]),
                  fz2 = dt / (2.0 * g.dx[2]);
     const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
-    const long long sx = 1, sy = g.s[0], sz = (long long)g.s[0] * g.s[1];
+    const unsigned bsx = 8u, bsy = (unsigned)g.s[0] * 8u, bsz = (unsigned)(g.s[0] * g.s[1]) * 8u;
 
     // plane-to-plane carries (values of the previous plane)
     // (zero until the first plane has been processed; the values derived from
@@ -207,14 +229,14 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     int err = 0;
 
     for (int q = T.z0 - 1; q <= T.z1; ++q) {
-        const long long oc = cell(g, xc, yc, q);
+        const unsigned boc = (unsigned)cell(g, xc, yc, q) * 8u;
         // ---------------------------------------------------- loads
-        const Face qx_lo = load_face(ws, QLO(0, 0), oc), qx_hi = load_face(ws, QHI(0, 0), oc);
-        const Face qy_lo = load_face(ws, QLO(1, 0), oc), qy_hi = load_face(ws, QHI(1, 0), oc);
-        const Face qz_lo = load_face(ws, QLO(2, 0), oc), qz_hi = load_face(ws, QHI(2, 0), oc);
-        const Flux dF1x = fdiff(load_flux(ws, F1F(0, 0), oc + sx), load_flux(ws, F1F(0, 0), oc));
-        const Flux dF1y = fdiff(load_flux(ws, F1F(1, 0), oc + sy), load_flux(ws, F1F(1, 0), oc));
-        const Flux dF1z = fdiff(load_flux(ws, F1F(2, 0), oc + sz), load_flux(ws, F1F(2, 0), oc));
+        const Face qx_lo = load_face_b(ws, QLO(0, 0), boc), qx_hi = load_face_b(ws, QHI(0, 0), boc);
+        const Face qy_lo = load_face_b(ws, QLO(1, 0), boc), qy_hi = load_face_b(ws, QHI(1, 0), boc);
+        const Face qz_lo = load_face_b(ws, QLO(2, 0), boc), qz_hi = load_face_b(ws, QHI(2, 0), boc);
+        const Flux dF1x = fdiff(load_flux_b(ws, F1F(0, 0), boc + bsx), load_flux_b(ws, F1F(0, 0), boc));
+        const Flux dF1y = fdiff(load_flux_b(ws, F1F(1, 0), boc + bsy), load_flux_b(ws, F1F(1, 0), boc));
+        const Flux dF1z = fdiff(load_flux_b(ws, F1F(2, 0), boc + bsz), load_flux_b(ws, F1F(2, 0), boc));
 
         // ---------------------------------------------------- A: high corner states
         int fb;
@@ -224,13 +246,13 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             putF(xa.v, 0, t, h);
             h = corner_state(qy_hi, dF1x, fx3, gm1, igm1, fb);  // (y|x)
             if (fb && hasU && inr(y + 1, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
-            putF(xa.v, 5, t, h);
+            putF(xa.v, 6, t, h);
             h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
             if (fb && hasR && inr(x + 1, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
             putF(xb.v, 0, t, h);
             h = corner_state(qy_hi, dF1z, fz3, gm1, igm1, fb);  // (y|z)
             if (fb && hasU && inr(y + 1, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
-            putF(xb.v, 5, t, h);
+            putF(xb.v, 6, t, h);
         }
         __syncthreads();
         // ---------------------------------------------------- B: round-2 fluxes
@@ -241,13 +263,13 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             F2xy = hllc(getF(xa.v, 0, tL), l, 0, gamma, igm1);
             l = corner_state(qy_lo, dF1x, fx3, gm1, igm1, fb);
             if (fb && hasD && inr(y, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
-            F2yx = hllc(getF(xa.v, 5, tD), l, 1, gamma, igm1);
+            F2yx = hllc(getF(xa.v, 6, tD), l, 1, gamma, igm1);
             l = corner_state(qx_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && hasL && inr(x, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
             F2xz = hllc(getF(xb.v, 0, tL), l, 0, gamma, igm1);
             l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && hasD && inr(y, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
-            F2yz = hllc(getF(xb.v, 5, tD), l, 1, gamma, igm1);
+            F2yz = hllc(getF(xb.v, 6, tD), l, 1, gamma, igm1);
         }
         // z-families: the flux through the z-face between q-1 and q
         {
@@ -294,10 +316,10 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             // final x and y states of plane q-1
             const int p = q - 1;
             const bool pv = p >= T.z0;  // plane p is finished in this segment
-            const long long op = oc - sz;
+            const unsigned bop = boc - bsz;
             Face xl, xh, yl, yh;
             {
-                const Face a = load_face(ws, QLO(0, 0), op), b = load_face(ws, QHI(0, 0), op);
+                const Face a = load_face_b(ws, QLO(0, 0), bop), b = load_face_b(ws, QHI(0, 0), bop);
                 xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
                 if (fb && pv && hasL && hasD && hasU && inr(x, 0, n0) && inr(y, 0, n1 - 1) &&
                     inr(p, 0, n2 - 1))
@@ -308,7 +330,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
                     err |= fb;
             }
             {
-                const Face a = load_face(ws, QLO(1, 0), op), b = load_face(ws, QHI(1, 0), op);
+                const Face a = load_face_b(ws, QLO(1, 0), bop), b = load_face_b(ws, QHI(1, 0), bop);
                 yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
                 if (fb && pv && hasD && hasL && hasR && inr(y, 0, n1) && inr(x, 0, n0 - 1) &&
                     inr(p, 0, n2 - 1))
@@ -323,10 +345,10 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             __syncthreads();
             // ------------------------------------------------ E/F: round-3 in-plane fluxes
             putF(xa.v, 0, t, xh);
-            putF(xa.v, 5, t, yh);
+            putF(xa.v, 6, t, yh);
             __syncthreads();
             const Flux F3x = hllc(getF(xa.v, 0, tL), xl, 0, gamma, igm1);
-            const Flux F3y = hllc(getF(xa.v, 5, tD), yl, 1, gamma, igm1);
+            const Flux F3y = hllc(getF(xa.v, 6, tD), yl, 1, gamma, igm1);
             putX(xb.v, 0, t, F3x);
             putX(xb.v, 5, t, F3y);
             __syncthreads();
@@ -339,14 +361,14 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
                                          {F3y.mw, Hy.mw}, {F3y.e, Hy.e}};
                 const double Fz[5][2] = {{F3z.m, F3zq.m}, {F3z.mu, F3zq.mu}, {F3z.mv, F3zq.mv},
                                          {F3z.mw, F3zq.mw}, {F3z.e, F3zq.e}};
-                const long long c0 = cell(g, x, y, p);
+                const unsigned bo = (unsigned)cell(g, x, y, p) * 8u;
                 double Uo[5], Us[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     double du = ax * (Fx[v][1] - Fx[v][0]);
                     du = du + ay * (Fy[v][1] - Fy[v][0]);
                     du = du + az * (Fz[v][1] - Fz[v][0]);
-                    Uo[v] = o.U[v * g.cs + c0];
+                    Uo[v] = ldb(o.U + v * g.cs, bo);
                     Us[v] = Uo[v] - du;
                 }
                 const double h = 0.5 * dt;
@@ -363,7 +385,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     if (!isfinite(Us[v])) err |= HYDRO_ERR_NONFINITE;
-                    o.Un[v * g.cs + c0] = Us[v];
+                    *(double *)((char *)(o.Un + v * g.cs) + bo) = Us[v];
                 }
                 if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
                 if (qn.p <= 0.0) err |= HYDRO_ERR_P;

@@ -362,8 +362,8 @@ bool box_valid(const hydro_box *b)
     }
     long long cs = 1;
     for (int d = 0; d < 3; ++d) cs *= (long long)b->n[d] + 2 * b->ng;
-    // block indices are 32-bit: keep every stage of one box below 2^31 blocks
-    return cs < (1LL << 36);
+    // the fused kernels address one component with 32-bit byte offsets
+    return cs < (1LL << 28);
 }
 
 bool params_valid(const hydro_params *p)

@@ -54,12 +54,6 @@ __device__ __forceinline__ double sound_ri(double gamma, double p, double ri)
     return sqrt((gamma * p) * ri);
 }
 
-// sound speed of a face state (HLLC input)
-__device__ __forceinline__ double sound(double gamma, double p, double r)
-{
-    return sqrt((gamma * p) / r);
-}
-
 // total energy density of a primitive state; igm1 = 1/(gamma-1)
 __device__ __forceinline__ double energy(double r, double u, double v, double w,
                                          double p, double igm1)
@@ -147,6 +141,7 @@ __device__ __forceinline__ double int_lo(const Parab &P, double lam, double dtdx
 // eigenvector; the low face mirrors this with the - wave and lam < 0.
 struct Face {
     double r, u, v, w, p;
+    double ri;  // 1/r, where a consumer needs it (HLLC inputs)
 };
 
 __device__ __forceinline__ void set_lab(Face &f, int d, double r, double un, double ut1,
@@ -239,7 +234,7 @@ __device__ __forceinline__ Flux phys_flux(const Face &q, double E, int d)
     return F;
 }
 
-// HLLC flux through a d-face.  The four cases (left state, left star, right
+// HLLC flux through a d-face (input states carry 1/rho in .ri).  The four cases (left state, left star, right
 // star, right state) are decided first; then only the chosen side's energy,
 // physical flux and (if needed) star correction F_K + S_K (U*_K - U_K) are
 // evaluated, each with exactly the arithmetic of its case.
@@ -248,8 +243,8 @@ __device__ __forceinline__ Flux hllc(const Face &L, const Face &R, int d, double
 {
     const double rL = L.r, uL = fvel(L, d), pL = L.p;
     const double rR = R.r, uR = fvel(R, d), pR = R.p;
-    const double cL = sound(gamma, pL, rL);
-    const double cR = sound(gamma, pR, rR);
+    const double cL = sound_ri(gamma, pL, L.ri);
+    const double cR = sound_ri(gamma, pR, R.ri);
     const double SL = dmin(uL - cL, uR - cR);
     const double SR = dmax(uL + cL, uR + cR);
     const double num = ((pR - pL) + (rL * uL) * (SL - uL)) - (rR * uR) * (SR - uR);
@@ -290,21 +285,25 @@ __device__ __forceinline__ Flux hllc(const Face &L, const Face &R, int d, double
 // ---------------------------------------------------------------- corrections
 
 // Corrected state prim(U(q) - ...).  V = corrected conserved state; when its
-// density or pressure is not positive, q is kept and bit 8 is raised.
+// density or pressure is not positive, q is kept and bit 8 is raised.  The
+// result carries 1/rho.
 __device__ __forceinline__ Face accept(const Face &q, double V0, double V1, double V2,
                                        double V3, double V4, double gm1, int &err)
 {
     Prim c = prim_of(V0, V1, V2, V3, V4, gm1);
+    Face f;
     if (c.r <= 0.0 || c.p <= 0.0) {
         err |= 8;
-        return q;
+        f = q;
+        f.ri = 1.0 / q.r;
+        return f;
     }
-    Face f;
     f.r = c.r;
     f.u = c.u;
     f.v = c.v;
     f.w = c.w;
     f.p = c.p;
+    f.ri = c.ri;
     return f;
 }
 

@@ -27,11 +27,30 @@ constexpr int kTPlane = 432;  // LDS cells of one plane: (BX+4)(BY+4) <= 432 for
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// stores of five components at a 32-bit byte offset from uniform field bases
+__device__ __forceinline__ void st5(const WS &ws, int base, unsigned bo, double a0, double a1,
+                                    double a2, double a3, double a4)
+{
+    *(double *)((char *)ws.f(base + 0) + bo) = a0;
+    *(double *)((char *)ws.f(base + 1) + bo) = a1;
+    *(double *)((char *)ws.f(base + 2) + bo) = a2;
+    *(double *)((char *)ws.f(base + 3) + bo) = a3;
+    *(double *)((char *)ws.f(base + 4) + bo) = a4;
+}
+__device__ __forceinline__ void stb(const WS &ws, int base, unsigned bo, const Face &f)
+{
+    st5(ws, base, bo, f.r, f.u, f.v, f.w, f.p);
+}
+__device__ __forceinline__ void stb(const WS &ws, int base, unsigned bo, const Flux &f)
+{
+    st5(ws, base, bo, f.m, f.mu, f.mv, f.mw, f.e);
+}
+
 __global__ void __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(2)))
 k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
 {
     __shared__ double pl[3][5][kTPlane];  // primitive planes (rho, u, v, w, p), ring of 3
-    __shared__ double xq[10][kTT];        // high-face x and y states for the round-1 fluxes
+    __shared__ double xq[12][kTT];        // high-face x and y states for the round-1 fluxes
     Box1 o = resolve(L);
     const Geo &g = o.g;
     const WS &ws = o.ws;
@@ -75,9 +94,9 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
             const int rx = r % RW, ry = r / RW;
             const int cx = clampi(x0 - 3 + rx, -ng, n0 + ng - 1);
             const int cy = clampi(y0 - 3 + ry, -ng, n1 + ng - 1);
-            const long long c0 = cell(g, cx, cy, zc);
-            Prim q = prim_of(o.U[c0], o.U[g.cs + c0], o.U[2 * g.cs + c0], o.U[3 * g.cs + c0],
-                             o.U[4 * g.cs + c0], gm1);
+            const unsigned bo = (unsigned)cell(g, cx, cy, zc) * 8u;
+            Prim q = prim_of(ldb(o.U, bo), ldb(o.U + g.cs, bo), ldb(o.U + 2 * g.cs, bo),
+                             ldb(o.U + 3 * g.cs, bo), ldb(o.U + 4 * g.cs, bo), gm1);
             pl[slot][0][r] = q.r;
             pl[slot][1][r] = q.u;
             pl[slot][2][r] = q.v;
@@ -133,6 +152,8 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         if (gx != 0.0) { zh.u = zh.u + h * gx; zl.u = zl.u + h * gx; }
         if (gy != 0.0) { zh.v = zh.v + h * gy; zl.v = zl.v + h * gy; }
         if (gz != 0.0) { zh.w = zh.w + h * gz; zl.w = zl.w + h * gz; }
+        zh.ri = 1.0 / zh.r;
+        zl.ri = 1.0 / zl.r;
         const Flux F1z = hllc(qz_hi_prev, zl, 2, gamma, igm1);
         qz_hi_prev = zh;
         if (p < z0) {  // warm-up plane: only the z high-face state is needed
@@ -177,28 +198,26 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
             xh.w = xh.w + h * gz; xl.w = xl.w + h * gz;
             yh.w = yh.w + h * gz; yl.w = yl.w + h * gz;
         }
+        xh.ri = 1.0 / xh.r;
+        xl.ri = 1.0 / xl.r;
+        yh.ri = 1.0 / yh.r;
+        yl.ri = 1.0 / yl.r;
         putF(xq, 0, t, xh);
-        putF(xq, 5, t, yh);
+        putF(xq, 6, t, yh);
         __syncthreads();
         const Flux F1x = hllc(getF(xq, 0, tL), xl, 0, gamma, igm1);
-        const Flux F1y = hllc(getF(xq, 5, tD), yl, 1, gamma, igm1);
+        const Flux F1y = hllc(getF(xq, 6, tD), yl, 1, gamma, igm1);
         if (inner) {
-            const long long c0 = cell(g, x, y, p);
-            ws.f(QHI(0, 0))[c0] = xh.r; ws.f(QHI(0, 1))[c0] = xh.u; ws.f(QHI(0, 2))[c0] = xh.v;
-            ws.f(QHI(0, 3))[c0] = xh.w; ws.f(QHI(0, 4))[c0] = xh.p;
-            ws.f(QLO(0, 0))[c0] = xl.r; ws.f(QLO(0, 1))[c0] = xl.u; ws.f(QLO(0, 2))[c0] = xl.v;
-            ws.f(QLO(0, 3))[c0] = xl.w; ws.f(QLO(0, 4))[c0] = xl.p;
-            ws.f(QHI(1, 0))[c0] = yh.r; ws.f(QHI(1, 1))[c0] = yh.u; ws.f(QHI(1, 2))[c0] = yh.v;
-            ws.f(QHI(1, 3))[c0] = yh.w; ws.f(QHI(1, 4))[c0] = yh.p;
-            ws.f(QLO(1, 0))[c0] = yl.r; ws.f(QLO(1, 1))[c0] = yl.u; ws.f(QLO(1, 2))[c0] = yl.v;
-            ws.f(QLO(1, 3))[c0] = yl.w; ws.f(QLO(1, 4))[c0] = yl.p;
-            ws.f(QHI(2, 0))[c0] = zh.r; ws.f(QHI(2, 1))[c0] = zh.u; ws.f(QHI(2, 2))[c0] = zh.v;
-            ws.f(QHI(2, 3))[c0] = zh.w; ws.f(QHI(2, 4))[c0] = zh.p;
-            ws.f(QLO(2, 0))[c0] = zl.r; ws.f(QLO(2, 1))[c0] = zl.u; ws.f(QLO(2, 2))[c0] = zl.v;
-            ws.f(QLO(2, 3))[c0] = zl.w; ws.f(QLO(2, 4))[c0] = zl.p;
-            if (x >= 0) store_flux(ws, F1F(0, 0), c0, F1x);
-            if (y >= 0) store_flux(ws, F1F(1, 0), c0, F1y);
-            if (p >= 0) store_flux(ws, F1F(2, 0), c0, F1z);
+            const unsigned bo = (unsigned)cell(g, x, y, p) * 8u;
+            stb(ws, QHI(0, 0), bo, xh);
+            stb(ws, QLO(0, 0), bo, xl);
+            stb(ws, QHI(1, 0), bo, yh);
+            stb(ws, QLO(1, 0), bo, yl);
+            stb(ws, QHI(2, 0), bo, zh);
+            stb(ws, QLO(2, 0), bo, zl);
+            if (x >= 0) stb(ws, F1F(0, 0), bo, F1x);
+            if (y >= 0) stb(ws, F1F(1, 0), bo, F1y);
+            if (p >= 0) stb(ws, F1F(2, 0), bo, F1z);
         }
         __syncthreads();
     }
