@@ -33,6 +33,31 @@ def lib():
         path = _build.LIB
         if not os.path.exists(path):
             _build.build()
+        _lib = _load(path)
+    return _lib
+
+
+class using:
+    """Context manager: route every oracle call to the library at ``path``
+    (a variant build, e.g. a deliberately broken one in a test)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _load(path):
+    if True:
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         bp = C.POINTER(OrcBox)
@@ -54,8 +79,7 @@ def lib():
         for f in ("orc_ppm_parabola", "orc_ppm_integrals", "orc_trace", "orc_hllc",
                   "orc_prim_of_cons", "orc_cons_of_prim"):
             getattr(L, f).restype = None
-        _lib = L
-    return _lib
+        return L
 
 
 def _dp(a):

@@ -1,0 +1,128 @@
+"""The pins catch plausible mistakes: each mutant below is the oracle's source
+with one deliberate error (a flipped sign, a dropped term, a wrong constant
+or operand), compiled on the CPU; the battery of pins of
+test_oracle_pieces.py / test_oracle_scheme.py is run against it and at least
+one pin must fail.  Nothing here touches a GPU."""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import test_oracle_pieces as P
+import test_oracle_scheme as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
+
+MUTANTS = {
+    "corner correction sign": (
+        "V[v] = Uq[v] - fac * (Fhi[v] - Flo[v]);",
+        "V[v] = Uq[v] + fac * (Fhi[v] - Flo[v]);"),
+    "final correction operand order": (
+        "V[v] = (Uq[v] - f1 * (A1[v] - A0[v])) - f2 * (B1[v] - B0[v]);",
+        "V[v] = (Uq[v] - f1 * (A0[v] - A1[v])) - f2 * (B1[v] - B0[v]);"),
+    "dropped curvature term at the low face": (
+        "return aL + (0.5 * s) * (dA + (1.0 - C23 * s) * a6);",
+        "return aL + (0.5 * s) * dA;"),
+    "tracing velocity sign": (
+        "f[1] = r_un + cor * am;",
+        "f[1] = r_un - cor * am;"),
+    "HLLC right wave speed min for max": (
+        "double SR = mx(uL + cL, uR + cR);",
+        "double SR = mn(uL + cL, uR + cR);"),
+    "reflect without momentum flip": (
+        "U[c * cs + dst] = (flip && c == 1 + d) ? -v : v;",
+        "U[c * cs + dst] = v;"),
+    "z flux divergence sign": (
+        "du = du + dtdx[2] * (fat(&F3[2], pz)[v] - fat(&F3[2], p)[v]);",
+        "du = du - dtdx[2] * (fat(&F3[2], pz)[v] - fat(&F3[2], p)[v]);"),
+    "gravity energy source term": (
+        "Us[4] = Us[4] + hg * (Un[1 + e] + mnew);",
+        "Us[4] = Us[4] + hg * (Un[1 + e] + Un[1 + e]);"),
+    "interface value constant": (
+        "double aL = 0.5 * (a[1] + a[2]) - (d0 - dm) * C6;",
+        "double aL = 0.5 * (a[1] + a[2]) - (d0 - dm) * C23;"),
+    "CFL number dropped": (
+        "*dt = pr->cfl * mn(",
+        "*dt = 1.0 * mn("),
+    "minmod-like slope bound": (
+        "return copysign(mn(mn(fabs(dc), 2.0 * fabs(dl)), 2.0 * fabs(dr)), dc);",
+        "return copysign(mn(mn(fabs(dc), fabs(dl)), 2.0 * fabs(dr)), dc);"),
+    "HLLC star normal momentum": (
+        "Us[1 + d] = chi * (rho * Ss);",
+        "Us[1 + d] = chi * (rho * uK);"),
+    "entropy wave amplitude sign": (
+        "double az = lam[1] > 0.0 ? drz - dpz * ics2 : 0.0;",
+        "double az = lam[1] > 0.0 ? drz + dpz * ics2 : 0.0;"),
+    "corner coupling factor dt/2 for dt/3": (
+        "const double fac = dt / (3.0 * b->dx[sd]);",
+        "const double fac = dt / (2.0 * b->dx[sd]);"),
+}
+
+# the pins, cheapest first; each raises AssertionError when it fails
+BATTERY = [
+    ("fill vs numpy.pad", lambda o: S.test_fill_ghosts_matches_numpy_pad(o, ((2, 1, 0), (2, 1, 0)))),
+    ("dt closed form", lambda o: S.test_dt_closed_form_sod(o)),
+    ("PPM cubic", lambda o: P.test_ppm_interfaces_exact_on_cubic(o)),
+    ("PPM monotone", lambda o: P.test_ppm_limited_parabola_monotone_and_conservative(o)),
+    ("PPM quadrature", lambda o: P.test_ppm_integral_matches_quadrature(o)),
+    ("trace entropy wave", lambda o: (P.test_trace_entropy_wave_is_upwind_average(o, 0.7),
+                                      P.test_trace_entropy_wave_is_upwind_average(o, -0.7))),
+    ("HLLC consistency", lambda o: P.test_hllc_consistency(o)),
+    ("HLLC mirror", lambda o: P.test_hllc_mirror_symmetry(o)),
+    ("HLLC contact", lambda o: (P.test_hllc_stationary_contact(o), P.test_hllc_moving_contact_is_upwind(o))),
+    ("uniform state", lambda o: S.test_uniform_state_preserved_bitwise(o)),
+    ("free fall", lambda o: S.test_free_fall_gravity_closed_form(o)),
+    ("Sod permutation", lambda o: S.test_sod_axis_permutation_bitwise(o, 2)),
+    ("Sod mirror", lambda o: S.test_sod_mirror_symmetry(o)),
+    ("conservation", lambda o: S.test_conservation_periodic(o, "kh")),
+    ("walls conserve", lambda o: S.test_reflecting_walls_conserve_mass_energy(o)),
+    ("CTU stability", lambda o: S.test_ctu_stable_near_unit_courant_number(o)),
+    ("sound waves in streams", lambda o: [S.test_sound_wave_in_stream_second_order(o, u, s)
+                                          for u, s in [(2.0, 1), (2.0, -1), (-2.0, 1),
+                                                       (-2.0, -1), (0.3, 1)]]),
+    ("Sod exact", lambda o: S.test_sod_against_exact_solution(o)),
+    ("smooth order 2-D", lambda o: S.test_smooth_advection_second_order_2d(o)),
+    ("smooth order 3-D", lambda o: S.test_smooth_advection_second_order_3d(o)),
+]
+
+
+def _build_mutant(name, tmp):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not found (or not unique): %s" % name
+    path = os.path.join(tmp, "hydro_oracle.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    hdr = os.path.join(ROOT, "oracle", "hydro_oracle.h")
+    lib = os.path.join(tmp, "libmutant.so")
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c11", "-shared", "-fPIC",
+                    "-w", "-I", os.path.dirname(hdr), "-o", lib, path, "-lm"], check=True)
+    return lib
+
+
+def _first_failing_pin(orc):
+    for label, check in BATTERY:
+        try:
+            check(orc)
+        except AssertionError:
+            return label
+        except (ValueError, MemoryError, FloatingPointError):
+            return label + " (error)"
+    return None
+
+
+def test_unmutated_oracle_passes_battery(orc):
+    assert _first_failing_pin(orc) is None
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(orc, name):
+    with tempfile.TemporaryDirectory() as tmp:
+        lib = _build_mutant(name, tmp)
+        with orc.using(lib):
+            caught = _first_failing_pin(orc)
+    print("%s: caught by %s" % (name, caught))
+    assert caught is not None, "no pin fails for the mutant '%s'" % name

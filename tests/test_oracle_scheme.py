@@ -317,3 +317,62 @@ def test_smooth_advection_second_order_3d(orc):
     order = math.log(e32 / e64, 2)
     assert order >= 1.75, (e32, e64, order)
     assert dp <= 1e-13 and du <= 1e-13
+
+
+# ----------------------------------------------------------------- CTU stability
+
+def test_ctu_stable_near_unit_courant_number(orc):
+    # the 3-D corner-transport-upwind scheme is stable for Courant numbers up
+    # to 1 in each direction (Colella 1990; Saltzman 1994): white-noise
+    # density carried diagonally at CFL 0.95 must not grow
+    n = 16
+    U, box, prm = inputs.advect((n, n, n), kvec=(1, 1, 1), vel=(1.0, 1.0, 1.0), amp=0.0)
+    rng = np.random.default_rng(0)
+    v = inputs.valid(U, box)
+    rho = 1.0 + 0.01 * rng.standard_normal(v[0].shape)
+    U = inputs.from_primitive(box, rho, 1.0, 1.0, 1.0, 1.0)
+    prm["cfl"] = 0.95
+    ob, op = _obox(orc, box), _oprm(orc, prm)
+    dev0 = np.max(np.abs(rho - 1.0))
+    R, _, err = orc.run(U, ob, op, 150)
+    assert err == 0
+    dev = np.max(np.abs(inputs.valid(R, box)[0] - 1.0))
+    assert np.isfinite(dev) and dev <= dev0, (dev0, dev)
+
+
+# ----------------------------------------------------------------- supersonic waves
+
+def _acoustic_l1(orc, n, U0, sign, tend=0.25, eps=1e-4):
+    """L1 error of a linear sound wave (+ or - family, sign = +1/-1) carried by
+    a uniform stream U0 along x, against its exact translation at U0 + sign c."""
+    g = 1.4
+    rho0, p0 = 1.0, 1.0
+    c0 = math.sqrt(g * p0 / rho0)
+    U, box, prm = inputs.advect((n, 4, 4), kvec=(1, 0, 0), vel=(U0, 0.0, 0.0), amp=0.0)
+    box["dx"] = (1.0 / n, 1.0 / n, 1.0 / n)
+    x = (np.arange(n) + 0.5) / n
+    s = np.sin(2 * np.pi * x)[None, None, :]
+    U = inputs.from_primitive(box, rho0 * (1 + eps * s), U0 + sign * eps * c0 * s, 0.0, 0.0,
+                              p0 * (1 + g * eps * s))
+    ob, op = _obox(orc, box), _oprm(orc, prm)
+    t = 0.0
+    while t < tend - 1e-14:
+        orc.fill_ghosts(U, ob)
+        dt = min(orc.estimate_dt(U, ob, op), tend - t)
+        Un = U.copy()
+        assert orc.advance_box(U, Un, ob, op, dt) == 0
+        U = Un
+        t += dt
+    xs = x - (U0 + sign * c0) * t
+    exact = rho0 * (1 + eps * np.sin(2 * np.pi * xs))
+    return np.mean(np.abs(inputs.valid(U, box)[0, 2, 2, :] - exact)) / eps
+
+
+@pytest.mark.parametrize("U0,sign", [(2.0, 1), (2.0, -1), (-2.0, 1), (-2.0, -1), (0.3, 1)])
+def test_sound_wave_in_stream_second_order(orc, U0, sign):
+    # linear sound waves of both families in sub- and supersonic streams: the
+    # traced states must be consistent for every sign of every wave speed
+    e32 = _acoustic_l1(orc, 32, U0, sign)
+    e64 = _acoustic_l1(orc, 64, U0, sign)
+    order = math.log(e32 / e64, 2)
+    assert order >= 1.8, (e32, e64, order)
