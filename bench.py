@@ -144,6 +144,7 @@ def time_level(hydro, torch, inputs, steps, warmup):
     ms_default = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup)
     ms_batched = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup, js)
     # the same boxes, one library call per box and stage (one stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     Us = [torch.tensor(u, device="cuda") for u in states]
     Uns = [torch.empty_like(u) for u in Us]
     ws = hydro.alloc_workspace(max(boxes, key=lambda b: hydro.workspace_bytes(b)))
