@@ -1,16 +1,19 @@
 """Tile-shape autotuner for batched levels of boxes.
 
-The two fused kernels of the step process a box in tiles of 256 columns
-(tbx x 256/tbx, tbx in {8, 16, 32}) marching over z-segments of tzs planes.
+The two fused kernels of the step (the trace kernel and the flux kernel)
+each process a box in tiles of 256 columns (tbx x 256/tbx, tbx in
+{8, 16, 32}) marching over z-segments of tzs planes.
 The best tile depends on the box shape: narrow boxes waste halo columns in
 wide tiles, short boxes want short z-segments to expose enough blocks, tall
 ones long segments to amortise the two warm-up planes.  The paper finds the
 same trade-off at the level of AMReX box sizes and tunes it empirically
 (Sec. IV-A, the best/worst box-width sweep); here it is tuned per box-shape
 class on the GPU, by timing a batched step of boxes of that class with each
-candidate tile, and the winners are written as the JSON table that
-hydro_plan_create accepts.  Results never depend on the tile (every cell's
-arithmetic is the same), only the speed does.
+candidate tile (the library's stage events give each kernel's own time, so
+the two kernels are tuned independently in the same runs), and the winners
+are written as the JSON table that hydro_plan_create accepts.  Results never
+depend on the tile (every cell's arithmetic is the same), only the speed
+does.
 """
 import json
 
@@ -18,6 +21,7 @@ from . import hydro, inputs
 
 TBX = (8, 16, 32)
 TZS = (8, 16, 32, 64, 128)
+STAGES = ("trace_flux1", "corner_final_update")
 
 
 def shape_key(n):
@@ -25,8 +29,9 @@ def shape_key(n):
 
 
 def table_json(table):
-    """JSON text of a {shape: (tbx, tzs)} table in the plan's format."""
-    return json.dumps({k: [int(v[0]), int(v[1])] for k, v in sorted(table.items())})
+    """JSON text of a {shape: (tbx, tzs) or (tbx1, tzs1, tbx2, tzs2)} table in
+    the plan's format."""
+    return json.dumps({k: [int(x) for x in v] for k, v in sorted(table.items())})
 
 
 def candidates(n):
@@ -35,6 +40,7 @@ def candidates(n):
 
 
 def _time_class(n, tiles, prm, nboxes, reps, torch):
+    """{tile: (trace-kernel ms, flux-kernel ms)} for a batch of boxes of shape n."""
     states, boxes = [], []
     for i in range(nboxes):
         U, box, _ = inputs.smooth(n, seed=1000 + i, dx=(1.0 / 64,) * 3)
@@ -44,15 +50,13 @@ def _time_class(n, tiles, prm, nboxes, reps, torch):
     for tb in tiles:
         lev = hydro.Level(states, boxes, prm, shared_dt=True,
                           autotune_json=table_json({shape_key(n): tb}))
-        lev.step()  # warm-up (and first-touch of the workspace)
+        lev.step()  # warm-up (and first touch of the workspace)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        timer = hydro.StageTimer()
         for _ in range(reps):
-            lev.step()
-        e1.record()
-        torch.cuda.synchronize()
-        out[tb] = e0.elapsed_time(e1) / reps
+            with timer:
+                lev.step()
+        out[tb] = tuple(timer.total_ms[s] / reps for s in STAGES)
         del lev
     return out
 
@@ -61,7 +65,8 @@ def tune(boxes, prm=None, max_boxes_per_class=64, min_cells_per_class=2 ** 21, r
          log=None):
     """Tune every box shape of ``boxes``.  Each class is timed on a batch of
     synthetic boxes of that shape (enough boxes to fill the GPU, at most
-    ``max_boxes_per_class``).  Returns ({shape: (tbx, tzs)}, timings)."""
+    ``max_boxes_per_class``); the trace and flux kernels each get their
+    fastest tile.  Returns ({shape: (tbx1, tzs1, tbx2, tzs2)}, timings)."""
     import torch
     prm = prm or inputs.params_desc()
     shapes = sorted({tuple(b["n"]) for b in boxes})
@@ -70,9 +75,11 @@ def tune(boxes, prm=None, max_boxes_per_class=64, min_cells_per_class=2 ** 21, r
         cells = n[0] * n[1] * n[2]
         nb = max(1, min(max_boxes_per_class, -(-min_cells_per_class // cells)))
         t = _time_class(n, candidates(n), prm, nb, reps, torch)
-        best = min(t, key=t.get)
-        table[shape_key(n)] = best
+        b1 = min(t, key=lambda k: t[k][0])
+        b2 = min(t, key=lambda k: t[k][1])
+        table[shape_key(n)] = (b1[0], b1[1], b2[0], b2[1])
         timings[shape_key(n)] = {"%d,%d" % k: v for k, v in t.items()}
         if log:
-            log("tile %s: best %s (%.3f ms for %d boxes)" % (shape_key(n), best, t[best], nb))
+            log("tiles %s: trace %s (%.3f ms), flux %s (%.3f ms), %d boxes"
+                % (shape_key(n), b1, t[b1][0], b2, t[b2][1], nb))
     return table, timings

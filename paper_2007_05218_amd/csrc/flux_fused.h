@@ -154,8 +154,8 @@ struct Tile {
 __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long nblk)
 {
     Tile T;
-    T.BX = g.tbx;
-    T.BY = kFT / g.tbx;
+    T.BX = g.tbx2;
+    T.BY = kFT / g.tbx2;
     T.TX = T.BX - 2;
     T.TY = T.BY - 2;
     const int ntx = (g.n[0] + T.TX - 1) / T.TX;
@@ -173,16 +173,16 @@ __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long n
     const int iz = (int)(t / nty);
     T.x0 = ix * T.TX;
     T.y0 = iy * T.TY;
-    T.z0 = iz * g.tzs;
-    T.z1 = min(g.n[2], T.z0 + g.tzs);
+    T.z0 = iz * g.tzs2;
+    T.z1 = min(g.n[2], T.z0 + g.tzs2);
     return T;
 }
 
 __host__ inline long long fused_blocks(const Geo &g)
 {
-    const int TX = g.tbx - 2, TY = kFT / g.tbx - 2;
+    const int TX = g.tbx2 - 2, TY = kFT / g.tbx2 - 2;
     long long ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
-    long long nzs = (g.n[2] + g.tzs - 1) / g.tzs;
+    long long nzs = (g.n[2] + g.tzs2 - 1) / g.tzs2;
     return ntx * nty * nzs;
 }
 
@@ -217,7 +217,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     const double fx2 = dt / (2.0 * g.dx[0]), fy2 = dt / (2.0 * g.dx[1]),
                  fz2 = dt / (2.0 * g.dx[2]);
     const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
-    const unsigned bsx = 8u, bsy = (unsigned)g.s[0] * 8u, bsz = (unsigned)(g.s[0] * g.s[1]) * 8u;
+    const unsigned bsz = (unsigned)(g.s[0] * g.s[1]) * 8u;
 
     // plane-to-plane carries (values of the previous plane)
     // (zero until the first plane has been processed; the values derived from
@@ -226,6 +226,8 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     Flux F2zx = {}, F2zy = {};    // (z|x), (z|y) fluxes through the plane's low z-face
     Flux dF2xz = {}, dF2yz = {};  // x-difference of (x|z), y-difference of (y|z) fluxes
     Flux F3z = {};                // round-3 flux through the plane's low z-face
+    // round-1 flux through the low z-face of the first plane
+    Flux F1zc = load_flux_b(ws, F1F(2, 0), (unsigned)cell(g, xc, yc, T.z0 - 1) * 8u);
     int err = 0;
 
     for (int q = T.z0 - 1; q <= T.z1; ++q) {
@@ -234,9 +236,19 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
         const Face qx_lo = load_face_b(ws, QLO(0, 0), boc), qx_hi = load_face_b(ws, QHI(0, 0), boc);
         const Face qy_lo = load_face_b(ws, QLO(1, 0), boc), qy_hi = load_face_b(ws, QHI(1, 0), boc);
         const Face qz_lo = load_face_b(ws, QLO(2, 0), boc), qz_hi = load_face_b(ws, QHI(2, 0), boc);
-        const Flux dF1x = fdiff(load_flux_b(ws, F1F(0, 0), boc + bsx), load_flux_b(ws, F1F(0, 0), boc));
-        const Flux dF1y = fdiff(load_flux_b(ws, F1F(1, 0), boc + bsy), load_flux_b(ws, F1F(1, 0), boc));
-        const Flux dF1z = fdiff(load_flux_b(ws, F1F(2, 0), boc + bsz), load_flux_b(ws, F1F(2, 0), boc));
+        // round-1 fluxes: each lane loads those at its own low faces; the high
+        // x/y faces are the neighbours' (exchanged through LDS), the high z
+        // face is the next plane's low one (carried to the next plane)
+        const Flux F1x = load_flux_b(ws, F1F(0, 0), boc), F1y = load_flux_b(ws, F1F(1, 0), boc);
+        const Flux F1zn = load_flux_b(ws, F1F(2, 0), boc + bsz);
+        putX(xa.v, 0, t, F1x);
+        putX(xa.v, 6, t, F1y);
+        __syncthreads();
+        const Flux dF1x = fdiff(getX(xa.v, 0, tR), F1x);
+        const Flux dF1y = fdiff(getX(xa.v, 6, tU), F1y);
+        const Flux dF1z = fdiff(F1zn, F1zc);
+        F1zc = F1zn;
+        __syncthreads();
 
         // ---------------------------------------------------- A: high corner states
         int fb;

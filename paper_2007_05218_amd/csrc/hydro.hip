@@ -49,8 +49,9 @@ struct Geo {
     long long cs;  // doubles per component (s0*s1*s2)
     double dx[3];
     int bc_lo[3], bc_hi[3];
-    int tbx;  // fused kernels: tile width in columns (block = 256 threads = tbx x 256/tbx)
-    int tzs;  // fused kernels: z-segment length per block
+    // tiles of the fused kernels (block = 256 threads = tbx x 256/tbx columns,
+    // marching over z-segments of tzs planes): trace kernel, flux kernel
+    int tbx1, tzs1, tbx2, tzs2;
 };
 
 // workspace fields: traced face states (direction d, high/low face,
@@ -111,14 +112,14 @@ __device__ __forceinline__ bool reg_cell(const Reg &r, long long t, int &i, int 
 __host__ inline long long stage_blocks(const Geo &g, int st)
 {
     if (st == ST_TRACE) {  // tiles of (tbx-1) x (256/tbx-1) columns over [-1, n+1)
-        const long long TX = g.tbx - 1, TY = 256 / g.tbx - 1;
+        const long long TX = g.tbx1 - 1, TY = 256 / g.tbx1 - 1;
         return ((g.n[0] + 2 + TX - 1) / TX) * ((g.n[1] + 2 + TY - 1) / TY) *
-               ((g.n[2] + 2 + g.tzs - 1) / g.tzs);
+               ((g.n[2] + 2 + g.tzs1 - 1) / g.tzs1);
     }
     if (st == ST_FLUX) {  // tiles of (tbx-2) x (256/tbx-2) columns over [0, n)
-        const long long TX = g.tbx - 2, TY = 256 / g.tbx - 2;
+        const long long TX = g.tbx2 - 2, TY = 256 / g.tbx2 - 2;
         return ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) *
-               ((g.n[2] + g.tzs - 1) / g.tzs);
+               ((g.n[2] + g.tzs2 - 1) / g.tzs2);
     }
     const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
     long long items = st == ST_FILL ? g.cs - nv : nv;
@@ -372,16 +373,29 @@ bool params_valid(const hydro_params *p)
            isfinite(p->grav[0]) && isfinite(p->grav[1]) && isfinite(p->grav[2]);
 }
 
-// Built-in tile choice for the fused kernels when no tuned table applies:
-// 16 x 16 columns (14 x 14 outputs); z-segments short enough that the box
-// yields at least ~2048 blocks (8 per CU), but no shorter than 8 planes.
+// Built-in tile choice for the fused kernels when no tuned table applies
+// (from a sweep on the 512^3 and 256^3 boxes): the trace kernel prefers wide
+// tiles (32 x 8 columns) and the flux kernel square ones (16 x 16); both
+// prefer z-segments of 16-32 planes, which expose more blocks and keep the
+// planes in flight in cache; a segment costs one (trace) or two (flux) extra
+// warm-up planes.
+int default_zs(long long tiles, int nz)
+{
+    long long nzs = (8192 + tiles - 1) / tiles;  // aim at >= 8192 blocks (32 per CU)
+    int zs = (int)((nz + nzs - 1) / nzs);
+    if (zs < 16) zs = 16;
+    if (zs > 32) zs = 32;
+    return zs;
+}
+
 void set_default_tiles(Geo &g)
 {
-    g.tbx = 16;
-    const long long tiles = (long long)((g.n[0] + 13) / 14) * ((g.n[1] + 13) / 14);
-    long long nzs = (2048 + tiles - 1) / tiles;
-    int zs = (int)((g.n[2] + nzs - 1) / nzs);
-    g.tzs = zs < 8 ? 8 : zs;
+    g.tbx1 = g.n[0] + 2 >= 62 ? 32 : 16;
+    const int t1x = g.tbx1 - 1, t1y = 256 / g.tbx1 - 1;
+    g.tzs1 = default_zs((long long)((g.n[0] + 2 + t1x - 1) / t1x) * ((g.n[1] + 2 + t1y - 1) / t1y),
+                        g.n[2] + 2);
+    g.tbx2 = 16;
+    g.tzs2 = default_zs((long long)((g.n[0] + 13) / 14) * ((g.n[1] + 13) / 14), g.n[2]);
 }
 
 bool tiles_valid(int tbx, int tzs) { return (tbx == 8 || tbx == 16 || tbx == 32) && tzs >= 1; }
@@ -461,14 +475,15 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
 
 // ---------------------------------------------------------------- tile table
 
-// A tuned tile table: a flat JSON object mapping a box shape "NXxNYxNZ" to a
-// pair [tbx, tzs] (tile width in columns, z-segment length), e.g.
-//   {"16x32x64": [16, 32], "64x64x64": [32, 16]}
+// A tuned tile table: a flat JSON object mapping a box shape "NXxNYxNZ" to
+// [tbx, tzs] (tile width in columns, z-segment length; both kernels) or
+// [tbx1, tzs1, tbx2, tzs2] (trace kernel, flux kernel), e.g.
+//   {"16x32x64": [16, 32], "64x64x64": [32, 64, 16, 64]}
 // as written by the package's autotuner.  Shapes not listed keep the
 // built-in choice.  Returns false on a syntax error or an invalid tile.
 struct TileRule {
     int n[3];
-    int tbx, tzs;
+    int t[4];  // tbx1, tzs1, tbx2, tzs2
 };
 
 bool parse_tiles(const char *js, std::vector<TileRule> &out)
@@ -502,13 +517,25 @@ bool parse_tiles(const char *js, std::vector<TileRule> &out)
         if (*c++ != ':') return false;
         ws();
         if (*c++ != '[') return false;
-        if (!num(r.tbx)) return false;
-        ws();
-        if (*c++ != ',') return false;
-        if (!num(r.tzs)) return false;
-        ws();
-        if (*c++ != ']') return false;
-        if (!tiles_valid(r.tbx, r.tzs)) return false;
+        int k = 0;
+        for (;;) {
+            if (k == 4 || !num(r.t[k])) return false;
+            ++k;
+            ws();
+            if (*c == ',') {
+                ++c;
+                continue;
+            }
+            if (*c++ != ']') return false;
+            break;
+        }
+        if (k == 2) {  // one tile for both kernels
+            r.t[2] = r.t[0];
+            r.t[3] = r.t[1];
+        } else if (k != 4) {
+            return false;
+        }
+        if (!tiles_valid(r.t[0], r.t[1]) || !tiles_valid(r.t[2], r.t[3])) return false;
         out.push_back(r);
         ws();
         if (*c == ',') {
@@ -629,8 +656,10 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
         Geo g = make_geo(&boxes[b]);
         for (const TileRule &r : rules)
             if (r.n[0] == g.n[0] && r.n[1] == g.n[1] && r.n[2] == g.n[2]) {
-                g.tbx = r.tbx;
-                g.tzs = r.tzs;
+                g.tbx1 = r.t[0];
+                g.tzs1 = r.t[1];
+                g.tbx2 = r.t[2];
+                g.tzs2 = r.t[3];
             }
         P->geos.push_back(g);
         wsoff[b] = (long long)(P->ws_bytes / sizeof(double));

@@ -54,7 +54,7 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     Box1 o = resolve(L);
     const Geo &g = o.g;
     const WS &ws = o.ws;
-    const int BX = g.tbx, BY = kTT / g.tbx, TX = BX - 1, TY = BY - 1;
+    const int BX = g.tbx1, BY = kTT / g.tbx1, TX = BX - 1, TY = BY - 1;
     const int RW = BX + 4, RH = BY + 4;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], ng = g.ng;
     // tiles cover the traced region [-1, n+1) of each axis
@@ -70,7 +70,7 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     const int iy = (int)(tt % nty);
     const int iz = (int)(tt / nty);
     const int x0 = -1 + ix * TX, y0 = -1 + iy * TY;
-    const int z0 = -1 + iz * g.tzs, z1 = min(n2 + 1, z0 + g.tzs);
+    const int z0 = -1 + iz * g.tzs1, z1 = min(n2 + 1, z0 + g.tzs1);
 
     const int t = threadIdx.x;
     const int tx = t % BX, ty = t / BX;
@@ -85,23 +85,41 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     const double dtdx = dt / g.dx[0], dtdy = dt / g.dx[1], dtdz = dt / g.dx[2];
     const double h = 0.5 * dt;
 
-    // region plane loader: cells (x0-3 .. x0+TX+1) x (y0-3 .. y0+TY+1) of plane z,
-    // indices clamped into the ghosted box (clamped cells feed only unused lanes)
-    auto load_plane = [&](int z) {
-        const int slot = (z + 6) % 3;
+    // Region plane of prims: cells (x0-3 .. x0+TX+1) x (y0-3 .. y0+TY+1) of
+    // plane z, indices clamped into the ghosted box (clamped cells feed only
+    // unused lanes).  Each thread owns region cells t and t+256; their
+    // conserved values are fetched one plane ahead into registers so the
+    // global-memory latency overlaps the tracing of the current plane.
+    const int nreg = RW * RH;
+    double pf[2][5];
+    auto fetch = [&](int z) {
         const int zc = clampi(z, -ng, n2 + ng - 1);
-        for (int r = t; r < RW * RH; r += kTT) {
-            const int rx = r % RW, ry = r / RW;
-            const int cx = clampi(x0 - 3 + rx, -ng, n0 + ng - 1);
-            const int cy = clampi(y0 - 3 + ry, -ng, n1 + ng - 1);
-            const unsigned bo = (unsigned)cell(g, cx, cy, zc) * 8u;
-            Prim q = prim_of(ldb(o.U, bo), ldb(o.U + g.cs, bo), ldb(o.U + 2 * g.cs, bo),
-                             ldb(o.U + 3 * g.cs, bo), ldb(o.U + 4 * g.cs, bo), gm1);
-            pl[slot][0][r] = q.r;
-            pl[slot][1][r] = q.u;
-            pl[slot][2][r] = q.v;
-            pl[slot][3][r] = q.w;
-            pl[slot][4][r] = q.p;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int r = t + m * kTT;
+            if (r < nreg) {
+                const int rx = r % RW, ry = r / RW;
+                const int cx = clampi(x0 - 3 + rx, -ng, n0 + ng - 1);
+                const int cy = clampi(y0 - 3 + ry, -ng, n1 + ng - 1);
+                const unsigned bo = (unsigned)cell(g, cx, cy, zc) * 8u;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) pf[m][v] = ldb(o.U + v * g.cs, bo);
+            }
+        }
+    };
+    auto commit = [&](int z) {
+        const int slot = (z + 6) % 3;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int r = t + m * kTT;
+            if (r < nreg) {
+                Prim q = prim_of(pf[m][0], pf[m][1], pf[m][2], pf[m][3], pf[m][4], gm1);
+                pl[slot][0][r] = q.r;
+                pl[slot][1][r] = q.u;
+                pl[slot][2][r] = q.v;
+                pl[slot][3][r] = q.w;
+                pl[slot][4][r] = q.p;
+            }
         }
     };
 
@@ -109,24 +127,25 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     double wr[5], wu[5], wv[5], ww[5], wp[5];
     const int p0 = z0 >= 0 ? z0 - 1 : z0;  // warm-up plane for the first z-face flux
     for (int z = p0 - 2; z <= p0 + 1; ++z) {
-        load_plane(z);
+        fetch(z);
+        commit(z);
         __syncthreads();
         const int slot = (z + 6) % 3;
         const int k = z - (p0 - 2) + 1;  // window index of plane z before the first shift
-        if (k >= 1) {
-            wr[k] = pl[slot][0][rc];
-            wu[k] = pl[slot][1][rc];
-            wv[k] = pl[slot][2][rc];
-            ww[k] = pl[slot][3][rc];
-            wp[k] = pl[slot][4][rc];
-        }
+        wr[k] = pl[slot][0][rc];
+        wu[k] = pl[slot][1][rc];
+        wv[k] = pl[slot][2][rc];
+        ww[k] = pl[slot][3][rc];
+        wp[k] = pl[slot][4][rc];
         __syncthreads();
     }
     wr[0] = wu[0] = wv[0] = ww[0] = wp[0] = 0.0;
+    fetch(p0 + 2);
 
     Face qz_hi_prev = {};
     for (int p = p0; p < z1; ++p) {
-        load_plane(p + 2);
+        commit(p + 2);
+        if (p + 1 < z1) fetch(p + 3);
         __syncthreads();
         {  // shift the window and append plane p+2
             const int slot = (p + 2 + 6) % 3;

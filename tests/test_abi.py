@@ -109,7 +109,9 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("js", ['{"16x16x16": [12, 8]}', '{"16x16x16": [16, 0]}', '{16x16x16: [16, 8]}',
-                                '{"16x16": [16, 8]}', '["16x16x16"]', '{"16x16x16": [16, 8]} x'])
+                                '{"16x16": [16, 8]}', '["16x16x16"]', '{"16x16x16": [16, 8]} x',
+                                '{"16x16x16": [16, 8, 32]}', '{"16x16x16": [16, 8, 32, 8, 8]}',
+                                '{"16x16x16": [16, 8, 24, 8]}'])
 def test_plan_rejects_bad_tile_tables(js):
     # the table is parsed before any device allocation, so this needs no GPU
     L = hydro.lib()
@@ -120,7 +122,7 @@ def test_plan_rejects_bad_tile_tables(js):
 
 def test_autotune_table_format():
     from paper_2007_05218_amd import autotune
-    js = autotune.table_json({"16x32x64": (16, 32), "64x64x64": (32, 64)})
-    assert js == '{"16x32x64": [16, 32], "64x64x64": [32, 64]}'
+    js = autotune.table_json({"16x32x64": (16, 32), "64x64x64": (32, 64, 16, 32)})
+    assert js == '{"16x32x64": [16, 32], "64x64x64": [32, 64, 16, 32]}'
     c = autotune.candidates((16, 32, 64))
     assert (8, 64) in c and (32, 8) in c and all(t[0] in (8, 16, 32) for t in c)

@@ -99,7 +99,7 @@ def test_tile_shapes_do_not_change_results(gpu):
     states, boxes, prm = inputs.level(nboxes=12, seed=8)
     shapes = {tuple(b["n"]) for b in boxes}
     res = []
-    for tb in [(8, 8), (16, 64), (32, 16)]:
+    for tb in [(8, 8), (16, 64), (32, 16, 8, 32), (16, 4, 32, 128)]:
         table = {autotune.shape_key(n): tb for n in shapes}
         lev = gpu.Level(states, boxes, prm, shared_dt=True,
                         autotune_json=autotune.table_json(table))
@@ -118,6 +118,6 @@ def test_autotuner_runs(gpu):
     table, timings = autotune.tune(boxes, max_boxes_per_class=4, min_cells_per_class=1,
                                    reps=1)
     assert set(table) == {"16x32x16", "32x16x64"}
-    for k, (tbx, tzs) in table.items():
-        assert tbx in (8, 16, 32) and tzs >= 1
+    for k, (tbx1, tzs1, tbx2, tzs2) in table.items():
+        assert tbx1 in (8, 16, 32) and tzs1 >= 1 and tbx2 in (8, 16, 32) and tzs2 >= 1
     gpu.Plan(boxes, autotune.table_json(table)).close()
