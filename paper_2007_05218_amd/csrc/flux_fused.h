@@ -7,7 +7,10 @@
 // fluxes.  Output: the new state of the tile's cells.  Nothing else goes
 // back to HBM: in-plane neighbour exchanges go through LDS, and the
 // z-direction couplings (fluxes through z-faces and the z-differences of
-// the (z|s) fluxes) are carried from plane to plane in registers.
+// the (z|s) fluxes) are carried from plane to plane in registers or, for
+// values a lane alone needs a plane later, in its own LDS slots (which keeps
+// the kernel within its register budget: spilled registers would go to
+// scratch memory and cost HBM traffic).
 //
 // Tile: a 256-thread block covers BX x BY columns (BX*BY = 256) of which the
 // inner (BX-2) x (BY-2) are output columns; the one-column ring supplies the
@@ -19,8 +22,10 @@
 //
 // Error bits: a transverse-corrected state raises the fallback bit only
 // where the whole-box step computes it (the flux it feeds lies in that
-// flux's region of the box) and where this tile computes it from valid data;
-// overlapping tiles may raise the same bit twice, which OR absorbs.
+// flux's region of the box) and where this tile computes it from valid data
+// (every neighbour exchange it depends on had the neighbour in the tile, and
+// every z-carry it uses was computed in this segment); overlapping tiles may
+// raise the same bit twice, which OR absorbs.
 #pragma once
 
 namespace {
@@ -193,6 +198,7 @@ __global__ void __launch_bounds__(kFT) __attribute__((amdgpu_waves_per_eu(HYDRO_
 k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_dev)
 {
     __shared__ XBuf xa, xb;
+    __shared__ double cz[15][kFT];  // own-lane carries: dF2xz, dF2yz, F3z of the previous plane
     Box1 o = resolve(L);
     const Geo &g = o.g;
     const WS &ws = o.ws;
@@ -206,8 +212,16 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     const int xc = min(x, n0), yc = min(y, n1);
     const int tL = tx >= 1 ? t - 1 : t, tR = tx + 1 < T.BX ? t + 1 : t;
     const int tD = ty >= 1 ? t - T.BX : t, tU = ty + 1 < T.BY ? t + T.BX : t;
-    const bool hasL = tx >= 1, hasR = tx + 1 < T.BX, hasD = ty >= 1, hasU = ty + 1 < T.BY;
+    // neighbour lanes present in the tile: a value that depends on an
+    // exchange with a missing neighbour is never used and raises no error bit
+    const bool hL = tx >= 1, hR = tx + 1 < T.BX, hD = ty >= 1, hU = ty + 1 < T.BY;
     const bool outc = tx >= 1 && tx <= T.TX && ty >= 1 && ty <= T.TY && x < n0 && y < n1;
+
+    // region tests of the whole-box step (where it computes each quantity)
+    const bool rx_f = inr(x, 0, n0), rx_fh = inr(x + 1, 0, n0), rx_c = inr(x, 0, n0 - 1),
+               rx_w = inr(x, -1, n0);
+    const bool ry_f = inr(y, 0, n1), ry_fh = inr(y + 1, 0, n1), ry_c = inr(y, 0, n1 - 1),
+               ry_w = inr(y, -1, n1);
 
     const double gm1 = gamma - 1.0;
     const double igm1 = 1.0 / gm1;
@@ -224,14 +238,13 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     // them in the first two planes of a segment are never used)
     Face c_zx_hi = {}, c_zy_hi = {}, fz_hi = {};  // corner (z|x), (z|y), final z: high face
     Flux F2zx = {}, F2zy = {};    // (z|x), (z|y) fluxes through the plane's low z-face
-    Flux dF2xz = {}, dF2yz = {};  // x-difference of (x|z), y-difference of (y|z) fluxes
-    Flux F3z = {};                // round-3 flux through the plane's low z-face
     // round-1 flux through the low z-face of the first plane
     Flux F1zc = load_flux_b(ws, F1F(2, 0), (unsigned)cell(g, xc, yc, T.z0 - 1) * 8u);
     int err = 0;
 
     for (int q = T.z0 - 1; q <= T.z1; ++q) {
         const unsigned boc = (unsigned)cell(g, xc, yc, q) * 8u;
+        const bool rz_c = inr(q, 0, n2 - 1), rz_w = inr(q, -1, n2);
         // ---------------------------------------------------- loads
         const Face qx_lo = load_face_b(ws, QLO(0, 0), boc), qx_hi = load_face_b(ws, QHI(0, 0), boc);
         const Face qy_lo = load_face_b(ws, QLO(1, 0), boc), qy_hi = load_face_b(ws, QHI(1, 0), boc);
@@ -244,8 +257,8 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
         putX(xa.v, 0, t, F1x);
         putX(xa.v, 6, t, F1y);
         __syncthreads();
-        const Flux dF1x = fdiff(getX(xa.v, 0, tR), F1x);
-        const Flux dF1y = fdiff(getX(xa.v, 6, tU), F1y);
+        const Flux dF1x = fdiff(getX(xa.v, 0, tR), getX(xa.v, 0, t));
+        const Flux dF1y = fdiff(getX(xa.v, 6, tU), getX(xa.v, 6, t));
         const Flux dF1z = fdiff(F1zn, F1zc);
         F1zc = F1zn;
         __syncthreads();
@@ -254,16 +267,16 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
         int fb;
         {
             Face h = corner_state(qx_hi, dF1y, fy3, gm1, igm1, fb);  // (x|y)
-            if (fb && hasR && inr(x + 1, 0, n0) && inr(y, 0, n1 - 1) && inr(q, -1, n2)) err |= fb;
+            if (fb && hU && rx_fh && ry_c && rz_w) err |= fb;
             putF(xa.v, 0, t, h);
             h = corner_state(qy_hi, dF1x, fx3, gm1, igm1, fb);  // (y|x)
-            if (fb && hasU && inr(y + 1, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
+            if (fb && hR && ry_fh && rx_c && rz_w) err |= fb;
             putF(xa.v, 6, t, h);
             h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
-            if (fb && hasR && inr(x + 1, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
+            if (fb && rx_fh && rz_c && ry_w) err |= fb;
             putF(xb.v, 0, t, h);
             h = corner_state(qy_hi, dF1z, fz3, gm1, igm1, fb);  // (y|z)
-            if (fb && hasU && inr(y + 1, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
+            if (fb && ry_fh && rz_c && rx_w) err |= fb;
             putF(xb.v, 6, t, h);
         }
         __syncthreads();
@@ -271,34 +284,32 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
         Flux F2xy, F2yx, F2xz, F2yz;
         {
             Face l = corner_state(qx_lo, dF1y, fy3, gm1, igm1, fb);
-            if (fb && hasL && inr(x, 0, n0) && inr(y, 0, n1 - 1) && inr(q, -1, n2)) err |= fb;
+            if (fb && hU && rx_f && ry_c && rz_w) err |= fb;
             F2xy = hllc(getF(xa.v, 0, tL), l, 0, gamma, igm1);
             l = corner_state(qy_lo, dF1x, fx3, gm1, igm1, fb);
-            if (fb && hasD && inr(y, 0, n1) && inr(x, 0, n0 - 1) && inr(q, -1, n2)) err |= fb;
+            if (fb && hR && ry_f && rx_c && rz_w) err |= fb;
             F2yx = hllc(getF(xa.v, 6, tD), l, 1, gamma, igm1);
             l = corner_state(qx_lo, dF1z, fz3, gm1, igm1, fb);
-            if (fb && hasL && inr(x, 0, n0) && inr(q, 0, n2 - 1) && inr(y, -1, n1)) err |= fb;
+            if (fb && rx_f && rz_c && ry_w) err |= fb;
             F2xz = hllc(getF(xb.v, 0, tL), l, 0, gamma, igm1);
             l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);
-            if (fb && hasD && inr(y, 0, n1) && inr(q, 0, n2 - 1) && inr(x, -1, n0)) err |= fb;
+            if (fb && ry_f && rz_c && rx_w) err |= fb;
             F2yz = hllc(getF(xb.v, 6, tD), l, 1, gamma, igm1);
         }
         // z-families: the flux through the z-face between q-1 and q
         {
-            const bool valid = q >= T.z0;  // the plane below was computed here
+            const bool rz_f = inr(q, 0, n2), rz_fh = inr(q + 1, 0, n2);
             Face l = corner_state(qz_lo, dF1x, fx3, gm1, igm1, fb);  // (z|x)
-            if (fb && valid && inr(q, 0, n2) && inr(x, 0, n0 - 1) && inr(y, -1, n1)) err |= fb;
+            if (fb && hR && rz_f && rx_c && ry_w) err |= fb;
             Flux Fzx = hllc(c_zx_hi, l, 2, gamma, igm1);
             Face h = corner_state(qz_hi, dF1x, fx3, gm1, igm1, fb);
-            if (fb && q + 1 <= T.z1 && inr(q + 1, 0, n2) && inr(x, 0, n0 - 1) && inr(y, -1, n1))
-                err |= fb;
+            if (fb && hR && rz_fh && rx_c && ry_w) err |= fb;
             c_zx_hi = h;
             l = corner_state(qz_lo, dF1y, fy3, gm1, igm1, fb);  // (z|y)
-            if (fb && valid && inr(q, 0, n2) && inr(y, 0, n1 - 1) && inr(x, -1, n0)) err |= fb;
+            if (fb && hU && rz_f && ry_c && rx_w) err |= fb;
             Flux Fzy = hllc(c_zy_hi, l, 2, gamma, igm1);
             h = corner_state(qz_hi, dF1y, fy3, gm1, igm1, fb);
-            if (fb && q + 1 <= T.z1 && inr(q + 1, 0, n2) && inr(y, 0, n1 - 1) && inr(x, -1, n0))
-                err |= fb;
+            if (fb && hU && rz_fh && ry_c && rx_w) err |= fb;
             c_zy_hi = h;
             // z-differences of the (z|s) fluxes of plane q-1
             const Flux dzx = fdiff(Fzx, F2zx), dzy = fdiff(Fzy, F2zy);
@@ -313,47 +324,42 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             __syncthreads();
             // ------------------------------------------------ D: final states
             // final z state of plane q
-            const Flux dxy = fdiff(getX(xa.v, 0, tR), F2xy);
-            const Flux dyx = fdiff(getX(xa.v, 5, tU), F2yx);
-            const bool zin = hasL && hasR && hasD && hasU && x < n0 && y < n1;
+            const Flux dxy = fdiff(getX(xa.v, 0, tR), getX(xa.v, 0, t));
+            const Flux dyx = fdiff(getX(xa.v, 5, tU), getX(xa.v, 5, t));
+            const bool zin = hL && hR && hD && hU && rx_c && ry_c;
             Face zl = final_state2(qz_lo, dxy, dyx, fx2, fy2, gm1, igm1, fb);
-            if (fb && zin && inr(q, 0, n2) && q >= T.z0 && x >= 0 && y >= 0) err |= fb;
+            if (fb && zin && rz_f) err |= fb;
             Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, igm1, fb);
-            if (fb && zin && inr(q + 1, 0, n2) && q + 1 <= T.z1 && x >= 0 && y >= 0) err |= fb;
+            if (fb && zin && rz_fh) err |= fb;
             Flux F3zq = hllc(fz_hi, zl, 2, gamma, igm1);
             fz_hi = zh;
             // differences of the in-plane (s|z) fluxes of plane q (used next plane)
-            const Flux dxz = fdiff(getX(xb.v, 0, tR), F2xz);
-            const Flux dyz = fdiff(getX(xb.v, 5, tU), F2yz);
+            const Flux dxz = fdiff(getX(xb.v, 0, tR), getX(xb.v, 0, t));
+            const Flux dyz = fdiff(getX(xb.v, 5, tU), getX(xb.v, 5, t));
             // final x and y states of plane q-1
             const int p = q - 1;
             const bool pv = p >= T.z0;  // plane p is finished in this segment
+            const bool rp_c = inr(p, 0, n2 - 1);
             const unsigned bop = boc - bsz;
             Face xl, xh, yl, yh;
             {
                 const Face a = load_face_b(ws, QLO(0, 0), bop), b = load_face_b(ws, QHI(0, 0), bop);
+                const Flux dF2yz = getX(cz, 5, t);
                 xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
-                if (fb && pv && hasL && hasD && hasU && inr(x, 0, n0) && inr(y, 0, n1 - 1) &&
-                    inr(p, 0, n2 - 1))
-                    err |= fb;
+                if (fb && pv && hD && hU && rx_f && ry_c && rp_c) err |= fb;
                 xh = final_state2(b, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
-                if (fb && pv && hasR && hasD && hasU && inr(x + 1, 0, n0) && inr(y, 0, n1 - 1) &&
-                    inr(p, 0, n2 - 1))
-                    err |= fb;
+                if (fb && pv && hD && hU && rx_fh && ry_c && rp_c) err |= fb;
             }
             {
                 const Face a = load_face_b(ws, QLO(1, 0), bop), b = load_face_b(ws, QHI(1, 0), bop);
+                const Flux dF2xz = getX(cz, 0, t);
                 yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
-                if (fb && pv && hasD && hasL && hasR && inr(y, 0, n1) && inr(x, 0, n0 - 1) &&
-                    inr(p, 0, n2 - 1))
-                    err |= fb;
+                if (fb && pv && hL && hR && ry_f && rx_c && rp_c) err |= fb;
                 yh = final_state2(b, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
-                if (fb && pv && hasU && hasL && hasR && inr(y + 1, 0, n1) && inr(x, 0, n0 - 1) &&
-                    inr(p, 0, n2 - 1))
-                    err |= fb;
+                if (fb && pv && hL && hR && ry_fh && rx_c && rp_c) err |= fb;
             }
-            dF2xz = dxz;
-            dF2yz = dyz;
+            putX(cz, 0, t, dxz);
+            putX(cz, 5, t, dyz);
             __syncthreads();
             // ------------------------------------------------ E/F: round-3 in-plane fluxes
             putF(xa.v, 0, t, xh);
@@ -371,6 +377,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
                                          {F3x.mw, Hx.mw}, {F3x.e, Hx.e}};
                 const double Fy[5][2] = {{F3y.m, Hy.m}, {F3y.mu, Hy.mu}, {F3y.mv, Hy.mv},
                                          {F3y.mw, Hy.mw}, {F3y.e, Hy.e}};
+                const Flux F3z = getX(cz, 10, t);
                 const double Fz[5][2] = {{F3z.m, F3zq.m}, {F3z.mu, F3zq.mu}, {F3z.mv, F3zq.mv},
                                          {F3z.mw, F3zq.mw}, {F3z.e, F3zq.e}};
                 const unsigned bo = (unsigned)cell(g, x, y, p) * 8u;
@@ -402,7 +409,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
                 if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
                 if (qn.p <= 0.0) err |= HYDRO_ERR_P;
             }
-            F3z = F3zq;
+            putX(cz, 10, t, F3zq);
             __syncthreads();
         }
     }
