@@ -1,10 +1,10 @@
 // flux_fused.h -- the second half of the CTU step in one kernel:
-// corner coupling + round-2 HLLC, final states + round-3 HLLC, conservative
-// update, for one box tile, marching along z.
+// round-1 HLLC, corner coupling + round-2 HLLC, final states + round-3 HLLC,
+// conservative update, for one box tile, marching along z.
 //
-// Inputs (HBM workspace, written by the trace and round-1 kernels): the
-// traced face states of every cell in all three directions and the round-1
-// fluxes.  Output: the new state of the tile's cells.  Nothing else goes
+// Input (HBM workspace, written by the trace kernel): the traced face states
+// of every cell in all three directions; the round-1 fluxes are solved here
+// from them.  Output: the new state of the tile's cells.  Nothing else goes
 // back to HBM: in-plane neighbour exchanges go through LDS, and the
 // z-direction couplings (fluxes through z-faces and the z-differences of
 // the (z|s) fluxes) are carried from plane to plane in registers or, for
@@ -33,7 +33,7 @@ namespace {
 constexpr int kFT = 256;  // threads of a fused-flux block
 
 struct XBuf {
-    double v[12][kFT];
+    double v[10][kFT];
 };
 
 __device__ __forceinline__ void put5(double (*b)[kFT], int k0, int t, double a0, double a1,
@@ -45,11 +45,11 @@ __device__ __forceinline__ void put5(double (*b)[kFT], int k0, int t, double a0,
     b[k0 + 3][t] = a3;
     b[k0 + 4][t] = a4;
 }
-// states are exchanged with their 1/rho (6 slots from k0)
+// states are exchanged without their 1/rho (5 slots from k0); the reader
+// forms it, as the writer did, as 1/rho
 __device__ __forceinline__ void putF(double (*b)[kFT], int k0, int t, const Face &f)
 {
     put5(b, k0, t, f.r, f.u, f.v, f.w, f.p);
-    b[k0 + 5][t] = f.ri;
 }
 __device__ __forceinline__ void putX(double (*b)[kFT], int k0, int t, const Flux &f)
 {
@@ -63,7 +63,7 @@ __device__ __forceinline__ Face getF(double (*b)[kFT], int k0, int t)
     f.v = b[k0 + 2][t];
     f.w = b[k0 + 3][t];
     f.p = b[k0 + 4][t];
-    f.ri = b[k0 + 5][t];
+    f.ri = 1.0 / f.r;
     return f;
 }
 __device__ __forceinline__ Flux getX(double (*b)[kFT], int k0, int t)
@@ -108,14 +108,10 @@ __device__ __forceinline__ Face load_face_b(const WS &ws, int base, unsigned bo)
     return f;
 }
 
-__device__ __forceinline__ Flux load_flux_b(const WS &ws, int base, unsigned bo)
+// a traced state with its 1/rho, as a Riemann problem takes it
+__device__ __forceinline__ Face with_ri(Face f)
 {
-    Flux f;
-    f.m = ldb(ws.f(base + 0), bo);
-    f.mu = ldb(ws.f(base + 1), bo);
-    f.mv = ldb(ws.f(base + 2), bo);
-    f.mw = ldb(ws.f(base + 3), bo);
-    f.e = ldb(ws.f(base + 4), bo);
+    f.ri = 1.0 / f.r;
     return f;
 }
 
@@ -198,7 +194,9 @@ __global__ void __launch_bounds__(kFT) __attribute__((amdgpu_waves_per_eu(HYDRO_
 k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_dev)
 {
     __shared__ XBuf xa, xb;
-    __shared__ double cz[15][kFT];  // own-lane carries: dF2xz, dF2yz, F3z of the previous plane
+    // own-lane carries: dF2xz, dF2yz, F3z of the previous plane, F1z through
+    // the current plane's low face
+    __shared__ double cz[20][kFT];
     Box1 o = resolve(L);
     const Geo &g = o.g;
     const WS &ws = o.ws;
@@ -238,78 +236,91 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     // them in the first two planes of a segment are never used)
     Face c_zx_hi = {}, c_zy_hi = {}, fz_hi = {};  // corner (z|x), (z|y), final z: high face
     Flux F2zx = {}, F2zy = {};    // (z|x), (z|y) fluxes through the plane's low z-face
-    // round-1 flux through the low z-face of the first plane
-    Flux F1zc = load_flux_b(ws, F1F(2, 0), (unsigned)cell(g, xc, yc, T.z0 - 1) * 8u);
     int err = 0;
 
     for (int q = T.z0 - 1; q <= T.z1; ++q) {
         const unsigned boc = (unsigned)cell(g, xc, yc, q) * 8u;
-        const bool rz_c = inr(q, 0, n2 - 1), rz_w = inr(q, -1, n2);
+        // (the (s|z) corner states of the warm-up plane use the round-1 z-flux
+        // below it, which this segment does not have: the previous segment
+        // covers them)
+        const bool rz_c = inr(q, 0, n2 - 1) && q >= T.z0, rz_w = inr(q, -1, n2);
         // ---------------------------------------------------- loads
         const Face qx_lo = load_face_b(ws, QLO(0, 0), boc), qx_hi = load_face_b(ws, QHI(0, 0), boc);
         const Face qy_lo = load_face_b(ws, QLO(1, 0), boc), qy_hi = load_face_b(ws, QHI(1, 0), boc);
         const Face qz_lo = load_face_b(ws, QLO(2, 0), boc), qz_hi = load_face_b(ws, QHI(2, 0), boc);
-        // round-1 fluxes: each lane loads those at its own low faces; the high
-        // x/y faces are the neighbours' (exchanged through LDS), the high z
-        // face is the next plane's low one (carried to the next plane)
-        const Flux F1x = load_flux_b(ws, F1F(0, 0), boc), F1y = load_flux_b(ws, F1F(1, 0), boc);
-        const Flux F1zn = load_flux_b(ws, F1F(2, 0), boc + bsz);
-        putX(xa.v, 0, t, F1x);
-        putX(xa.v, 6, t, F1y);
+        // ---------------------------------------------------- round-1 fluxes
+        // through each lane's low x/y faces (the low neighbour's high state
+        // comes through LDS) and through the plane's high z-face; the x/y
+        // differences take the high neighbour's flux through LDS, the z
+        // difference the flux carried from the plane below
+        putF(xa.v, 0, t, qx_hi);
+        putF(xa.v, 5, t, qy_hi);
+        const Flux F1zn = hllc(with_ri(qz_hi),
+                               with_ri(load_face_b(ws, QLO(2, 0), boc + bsz)),  // next plane
+                               2, gamma, igm1);
         __syncthreads();
-        const Flux dF1x = fdiff(getX(xa.v, 0, tR), getX(xa.v, 0, t));
-        const Flux dF1y = fdiff(getX(xa.v, 6, tU), getX(xa.v, 6, t));
-        const Flux dF1z = fdiff(F1zn, F1zc);
-        F1zc = F1zn;
+        {
+            const Flux F1x = hllc(getF(xa.v, 0, tL), with_ri(qx_lo), 0, gamma, igm1);
+            const Flux F1y = hllc(getF(xa.v, 5, tD), with_ri(qy_lo), 1, gamma, igm1);
+            putX(xb.v, 0, t, F1x);
+            putX(xb.v, 5, t, F1y);
+        }
+        __syncthreads();
+        const Flux dF1x = fdiff(getX(xb.v, 0, tR), getX(xb.v, 0, t));
+        const Flux dF1y = fdiff(getX(xb.v, 5, tU), getX(xb.v, 5, t));
+        // (the round-1 z-flux carried from the plane below is never used
+        // before the first plane's)
+        const Flux dF1z = fdiff(F1zn, getX(cz, 15, t));
+        putX(cz, 15, t, F1zn);
         __syncthreads();
 
         // ---------------------------------------------------- A: high corner states
         int fb;
         {
             Face h = corner_state(qx_hi, dF1y, fy3, gm1, igm1, fb);  // (x|y)
-            if (fb && hU && rx_fh && ry_c && rz_w) err |= fb;
+            if (fb && hD && hU && rx_fh && ry_c && rz_w) err |= fb;
             putF(xa.v, 0, t, h);
             h = corner_state(qy_hi, dF1x, fx3, gm1, igm1, fb);  // (y|x)
-            if (fb && hR && ry_fh && rx_c && rz_w) err |= fb;
-            putF(xa.v, 6, t, h);
+            if (fb && hL && hR && ry_fh && rx_c && rz_w) err |= fb;
+            putF(xa.v, 5, t, h);
             h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
             if (fb && rx_fh && rz_c && ry_w) err |= fb;
             putF(xb.v, 0, t, h);
             h = corner_state(qy_hi, dF1z, fz3, gm1, igm1, fb);  // (y|z)
             if (fb && ry_fh && rz_c && rx_w) err |= fb;
-            putF(xb.v, 6, t, h);
+            putF(xb.v, 5, t, h);
         }
         __syncthreads();
         // ---------------------------------------------------- B: round-2 fluxes
         Flux F2xy, F2yx, F2xz, F2yz;
         {
             Face l = corner_state(qx_lo, dF1y, fy3, gm1, igm1, fb);
-            if (fb && hU && rx_f && ry_c && rz_w) err |= fb;
+            if (fb && hD && hU && rx_f && ry_c && rz_w) err |= fb;
             F2xy = hllc(getF(xa.v, 0, tL), l, 0, gamma, igm1);
             l = corner_state(qy_lo, dF1x, fx3, gm1, igm1, fb);
-            if (fb && hR && ry_f && rx_c && rz_w) err |= fb;
-            F2yx = hllc(getF(xa.v, 6, tD), l, 1, gamma, igm1);
+            if (fb && hL && hR && ry_f && rx_c && rz_w) err |= fb;
+            F2yx = hllc(getF(xa.v, 5, tD), l, 1, gamma, igm1);
             l = corner_state(qx_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && rx_f && rz_c && ry_w) err |= fb;
             F2xz = hllc(getF(xb.v, 0, tL), l, 0, gamma, igm1);
             l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && ry_f && rz_c && rx_w) err |= fb;
-            F2yz = hllc(getF(xb.v, 6, tD), l, 1, gamma, igm1);
+            F2yz = hllc(getF(xb.v, 5, tD), l, 1, gamma, igm1);
         }
         // z-families: the flux through the z-face between q-1 and q
         {
             const bool rz_f = inr(q, 0, n2), rz_fh = inr(q + 1, 0, n2);
             Face l = corner_state(qz_lo, dF1x, fx3, gm1, igm1, fb);  // (z|x)
-            if (fb && hR && rz_f && rx_c && ry_w) err |= fb;
+            if (fb && hL && hR && rz_f && rx_c && ry_w) err |= fb;
             Flux Fzx = hllc(c_zx_hi, l, 2, gamma, igm1);
             Face h = corner_state(qz_hi, dF1x, fx3, gm1, igm1, fb);
-            if (fb && hR && rz_fh && rx_c && ry_w) err |= fb;
+            if (fb && hL && hR && rz_fh && rx_c && ry_w) err |= fb;
             c_zx_hi = h;
             l = corner_state(qz_lo, dF1y, fy3, gm1, igm1, fb);  // (z|y)
-            if (fb && hU && rz_f && ry_c && rx_w) err |= fb;
+            if (fb && hD && hU && rz_f && ry_c && rx_w) err |= fb;
             Flux Fzy = hllc(c_zy_hi, l, 2, gamma, igm1);
             h = corner_state(qz_hi, dF1y, fy3, gm1, igm1, fb);
-            if (fb && hU && rz_fh && ry_c && rx_w) err |= fb;
+            if (fb && hD && hU && rz_fh && ry_c && rx_w) err |= fb;
             c_zy_hi = h;
             // z-differences of the (z|s) fluxes of plane q-1
             const Flux dzx = fdiff(Fzx, F2zx), dzy = fdiff(Fzy, F2zy);
@@ -363,10 +374,10 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             __syncthreads();
             // ------------------------------------------------ E/F: round-3 in-plane fluxes
             putF(xa.v, 0, t, xh);
-            putF(xa.v, 6, t, yh);
+            putF(xa.v, 5, t, yh);
             __syncthreads();
             const Flux F3x = hllc(getF(xa.v, 0, tL), xl, 0, gamma, igm1);
-            const Flux F3y = hllc(getF(xa.v, 6, tD), yl, 1, gamma, igm1);
+            const Flux F3y = hllc(getF(xa.v, 5, tD), yl, 1, gamma, igm1);
             putX(xb.v, 0, t, F3x);
             putX(xb.v, 5, t, F3y);
             __syncthreads();

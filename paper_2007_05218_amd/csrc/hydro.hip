@@ -55,12 +55,10 @@ struct Geo {
 };
 
 // workspace fields: traced face states (direction d, high/low face,
-// component v) and round-1 fluxes (face normal d, component v), each a dense
-// ghosted array like one state component
+// component v), each a dense ghosted array like one state component
 __host__ __device__ constexpr int QHI(int d, int v) { return d * 10 + v; }
 __host__ __device__ constexpr int QLO(int d, int v) { return d * 10 + 5 + v; }
-__host__ __device__ constexpr int F1F(int d, int v) { return 30 + d * 5 + v; }
-constexpr int kFields = 45;
+constexpr int kFields = 30;
 
 // stages (block-count prefix arrays are kept per stage)
 enum { ST_FILL = 0, ST_DT = 1, ST_TRACE = 2, ST_FLUX = 3, ST_COUNT = 4 };
@@ -111,8 +109,8 @@ __device__ __forceinline__ bool reg_cell(const Reg &r, long long t, int &i, int 
 // blocks of one box in a stage
 __host__ inline long long stage_blocks(const Geo &g, int st)
 {
-    if (st == ST_TRACE) {  // tiles of (tbx-1) x (256/tbx-1) columns over [-1, n+1)
-        const long long TX = g.tbx1 - 1, TY = 256 / g.tbx1 - 1;
+    if (st == ST_TRACE) {  // tiles of tbx x 256/tbx columns over [-1, n+1)
+        const long long TX = g.tbx1, TY = 256 / g.tbx1;
         return ((g.n[0] + 2 + TX - 1) / TX) * ((g.n[1] + 2 + TY - 1) / TY) *
                ((g.n[2] + 2 + g.tzs1 - 1) / g.tzs1);
     }
@@ -391,7 +389,7 @@ int default_zs(long long tiles, int nz)
 void set_default_tiles(Geo &g)
 {
     g.tbx1 = g.n[0] + 2 >= 62 ? 32 : 16;
-    const int t1x = g.tbx1 - 1, t1y = 256 / g.tbx1 - 1;
+    const int t1x = g.tbx1, t1y = 256 / g.tbx1;
     g.tzs1 = default_zs((long long)((g.n[0] + 2 + t1x - 1) / t1x) * ((g.n[1] + 2 + t1y - 1) / t1y),
                         g.n[2] + 2);
     g.tbx2 = 16;

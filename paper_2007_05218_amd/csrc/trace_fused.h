@@ -1,11 +1,13 @@
 // trace_fused.h -- the first half of the CTU step in one kernel: primitive
 // variables, PPM reconstruction and characteristic tracing in all three
-// directions (with the half-step gravity kick), and the round-1 HLLC fluxes,
-// for one box tile, marching along z.
+// directions (with the half-step gravity kick), for one box tile, marching
+// along z.
 //
 // Output (HBM workspace): the traced face states of every cell one beyond
-// the valid region, and the round-1 fluxes at every face the corner step
-// reads -- the inputs of the fused flux kernel.  Each cell's primitives are
+// the valid region -- the input of the fused flux kernel, which also solves
+// the round-1 Riemann problems from them (a round-1 flux costs less to
+// recompute there than its five doubles cost to store here and read back
+// there).  Each cell's primitives are
 // computed once per block: a plane of the tile plus a two-cell ring enters
 // an LDS ring of three planes (the x/y stencils read the centre plane from
 // it) and each column copies its own values into a five-plane register
@@ -13,11 +15,9 @@
 // paper's Sec. III with the neighbouring slopes staged on chip instead of
 // recomputed from global memory.
 //
-// Tile: a 256-thread block covers BX x BY columns: output columns
-// [x0, x0+BX-1) x [y0, y0+BY-1) of the traced region plus one column on
-// the low side of each axis, whose high-face state the round-1 flux on the
-// first output column needs.  Blocks march over planes [z0, z1) of the
-// traced region, with one warm-up plane below z0 for the z-face flux.
+// Tile: a 256-thread block covers BX x BY output columns
+// [x0, x0+BX) x [y0, y0+BY) of the traced region and marches over its
+// planes [z0, z1).
 #pragma once
 
 namespace {
@@ -41,24 +41,19 @@ __device__ __forceinline__ void stb(const WS &ws, int base, unsigned bo, const F
 {
     st5(ws, base, bo, f.r, f.u, f.v, f.w, f.p);
 }
-__device__ __forceinline__ void stb(const WS &ws, int base, unsigned bo, const Flux &f)
-{
-    st5(ws, base, bo, f.m, f.mu, f.mv, f.mw, f.e);
-}
 
-__global__ void __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(3)))
 k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
 {
     __shared__ double pl[3][5][kTPlane];  // primitive planes (rho, u, v, w, p), ring of 3
-    __shared__ double xq[12][kTT];        // high-face x and y states for the round-1 fluxes
     Box1 o = resolve(L);
     const Geo &g = o.g;
     const WS &ws = o.ws;
-    const int BX = g.tbx1, BY = kTT / g.tbx1, TX = BX - 1, TY = BY - 1;
+    const int BX = g.tbx1, BY = kTT / g.tbx1;
     const int RW = BX + 4, RH = BY + 4;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], ng = g.ng;
     // tiles cover the traced region [-1, n+1) of each axis
-    const int ntx = (n0 + 2 + TX - 1) / TX, nty = (n1 + 2 + TY - 1) / TY;
+    const int ntx = (n0 + 2 + BX - 1) / BX, nty = (n1 + 2 + BY - 1) / BY;
     long long tt;
     {
         long long per = o.nblk / 8, rem = o.nblk % 8;
@@ -69,23 +64,21 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     tt /= ntx;
     const int iy = (int)(tt % nty);
     const int iz = (int)(tt / nty);
-    const int x0 = -1 + ix * TX, y0 = -1 + iy * TY;
+    const int x0 = -1 + ix * BX, y0 = -1 + iy * BY;
     const int z0 = -1 + iz * g.tzs1, z1 = min(n2 + 1, z0 + g.tzs1);
 
     const int t = threadIdx.x;
     const int tx = t % BX, ty = t / BX;
-    const int x = x0 - 1 + tx, y = y0 - 1 + ty;  // this thread's column
-    const bool inner = tx >= 1 && ty >= 1 && x <= n0 && y <= n1;
-    const int tL = tx >= 1 ? t - 1 : t, tD = ty >= 1 ? t - BX : t;
+    const int x = x0 + tx, y = y0 + ty;  // this thread's column
+    const bool inner = x <= n0 && y <= n1;
     const int rc = (ty + 2) * RW + (tx + 2);  // own column in the plane buffer
 
-    const double gm1 = gamma - 1.0;
-    const double igm1 = 1.0 / gm1;
     const double dt = *o.dt;
     const double dtdx = dt / g.dx[0], dtdy = dt / g.dx[1], dtdz = dt / g.dx[2];
     const double h = 0.5 * dt;
+    const double gm1 = gamma - 1.0;
 
-    // Region plane of prims: cells (x0-3 .. x0+TX+1) x (y0-3 .. y0+TY+1) of
+    // Region plane of prims: cells (x0-2 .. x0+BX+1) x (y0-2 .. y0+BY+1) of
     // plane z, indices clamped into the ghosted box (clamped cells feed only
     // unused lanes).  Each thread owns region cells t and t+256; their
     // conserved values are fetched one plane ahead into registers so the
@@ -99,8 +92,8 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
             const int r = t + m * kTT;
             if (r < nreg) {
                 const int rx = r % RW, ry = r / RW;
-                const int cx = clampi(x0 - 3 + rx, -ng, n0 + ng - 1);
-                const int cy = clampi(y0 - 3 + ry, -ng, n1 + ng - 1);
+                const int cx = clampi(x0 - 2 + rx, -ng, n0 + ng - 1);
+                const int cy = clampi(y0 - 2 + ry, -ng, n1 + ng - 1);
                 const unsigned bo = (unsigned)cell(g, cx, cy, zc) * 8u;
 #pragma unroll
                 for (int v = 0; v < 5; ++v) pf[m][v] = ldb(o.U + v * g.cs, bo);
@@ -125,13 +118,12 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
 
     // z-window of the own column: planes p-2 .. p+2 (index 0 .. 4)
     double wr[5], wu[5], wv[5], ww[5], wp[5];
-    const int p0 = z0 >= 0 ? z0 - 1 : z0;  // warm-up plane for the first z-face flux
-    for (int z = p0 - 2; z <= p0 + 1; ++z) {
+    for (int z = z0 - 2; z <= z0 + 1; ++z) {
         fetch(z);
         commit(z);
         __syncthreads();
         const int slot = (z + 6) % 3;
-        const int k = z - (p0 - 2) + 1;  // window index of plane z before the first shift
+        const int k = z - (z0 - 2) + 1;  // window index of plane z before the first shift
         wr[k] = pl[slot][0][rc];
         wu[k] = pl[slot][1][rc];
         wv[k] = pl[slot][2][rc];
@@ -140,10 +132,9 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         __syncthreads();
     }
     wr[0] = wu[0] = wv[0] = ww[0] = wp[0] = 0.0;
-    fetch(p0 + 2);
+    fetch(z0 + 2);
 
-    Face qz_hi_prev = {};
-    for (int p = p0; p < z1; ++p) {
+    for (int p = z0; p < z1; ++p) {
         commit(p + 2);
         if (p + 1 < z1) fetch(p + 3);
         __syncthreads();
@@ -165,23 +156,19 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         }
         const double ri = 1.0 / wr[2];  // as the cell's primitive conversion forms it
         const double c = sound_ri(gamma, wp[2], ri);
+        const int slot = (p + 6) % 3;
+        Face hi, lo;
+        const unsigned bo = (unsigned)cell(g, inner ? x : n0, inner ? y : n1, p) * 8u;
         // ------------------------------------------------ z trace
-        Face zh, zl;
-        trace_cell(wr, ww, wu, wv, wp, c, ri, 2, dtdz, zh, zl);
-        if (gx != 0.0) { zh.u = zh.u + h * gx; zl.u = zl.u + h * gx; }
-        if (gy != 0.0) { zh.v = zh.v + h * gy; zl.v = zl.v + h * gy; }
-        if (gz != 0.0) { zh.w = zh.w + h * gz; zl.w = zl.w + h * gz; }
-        zh.ri = 1.0 / zh.r;
-        zl.ri = 1.0 / zl.r;
-        const Flux F1z = hllc(qz_hi_prev, zl, 2, gamma, igm1);
-        qz_hi_prev = zh;
-        if (p < z0) {  // warm-up plane: only the z high-face state is needed
-            __syncthreads();
-            continue;
+        trace_cell(wr, ww, wu, wv, wp, c, ri, 2, dtdz, hi, lo);
+        if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
+        if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
+        if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
+        if (inner) {
+            stb(ws, QHI(2, 0), bo, hi);
+            stb(ws, QLO(2, 0), bo, lo);
         }
         // ------------------------------------------------ x and y traces of plane p
-        const int slot = (p + 6) % 3;
-        Face xh, xl, yh, yl;
         {
             double rs[5], a1[5], a2[5], a3[5], ps[5];
 #pragma unroll
@@ -193,7 +180,17 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
                 a3[m] = pl[slot][3][r];
                 ps[m] = pl[slot][4][r];
             }
-            trace_cell(rs, a1, a2, a3, ps, c, ri, 0, dtdx, xh, xl);
+            trace_cell(rs, a1, a2, a3, ps, c, ri, 0, dtdx, hi, lo);
+        }
+        if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
+        if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
+        if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
+        if (inner) {
+            stb(ws, QHI(0, 0), bo, hi);
+            stb(ws, QLO(0, 0), bo, lo);
+        }
+        {
+            double rs[5], a1[5], a2[5], a3[5], ps[5];
 #pragma unroll
             for (int m = 0; m < 5; ++m) {
                 const int r = rc + (m - 2) * RW;
@@ -203,40 +200,14 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
                 a3[m] = pl[slot][3][r];
                 ps[m] = pl[slot][4][r];
             }
-            trace_cell(rs, a1, a2, a3, ps, c, ri, 1, dtdy, yh, yl);
+            trace_cell(rs, a1, a2, a3, ps, c, ri, 1, dtdy, hi, lo);
         }
-        if (gx != 0.0) {
-            xh.u = xh.u + h * gx; xl.u = xl.u + h * gx;
-            yh.u = yh.u + h * gx; yl.u = yl.u + h * gx;
-        }
-        if (gy != 0.0) {
-            xh.v = xh.v + h * gy; xl.v = xl.v + h * gy;
-            yh.v = yh.v + h * gy; yl.v = yl.v + h * gy;
-        }
-        if (gz != 0.0) {
-            xh.w = xh.w + h * gz; xl.w = xl.w + h * gz;
-            yh.w = yh.w + h * gz; yl.w = yl.w + h * gz;
-        }
-        xh.ri = 1.0 / xh.r;
-        xl.ri = 1.0 / xl.r;
-        yh.ri = 1.0 / yh.r;
-        yl.ri = 1.0 / yl.r;
-        putF(xq, 0, t, xh);
-        putF(xq, 6, t, yh);
-        __syncthreads();
-        const Flux F1x = hllc(getF(xq, 0, tL), xl, 0, gamma, igm1);
-        const Flux F1y = hllc(getF(xq, 6, tD), yl, 1, gamma, igm1);
+        if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
+        if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
+        if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
         if (inner) {
-            const unsigned bo = (unsigned)cell(g, x, y, p) * 8u;
-            stb(ws, QHI(0, 0), bo, xh);
-            stb(ws, QLO(0, 0), bo, xl);
-            stb(ws, QHI(1, 0), bo, yh);
-            stb(ws, QLO(1, 0), bo, yl);
-            stb(ws, QHI(2, 0), bo, zh);
-            stb(ws, QLO(2, 0), bo, zl);
-            if (x >= 0) stb(ws, F1F(0, 0), bo, F1x);
-            if (y >= 0) stb(ws, F1F(1, 0), bo, F1y);
-            if (p >= 0) stb(ws, F1F(2, 0), bo, F1z);
+            stb(ws, QHI(1, 0), bo, hi);
+            stb(ws, QLO(1, 0), bo, lo);
         }
         __syncthreads();
     }
