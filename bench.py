@@ -39,10 +39,10 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_NOFMA = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
 # oracle stages computed by each kernel group of the library's advance
-KERNEL_STAGES = {"trace_flux1": ["prim", "trace", "flux1"],
-                 "corner_final_update": ["corner_flux2", "final_flux3", "update"]}
+KERNEL_STAGES = {"trace": ["prim", "trace"],
+                 "flux_update": ["flux1", "corner_flux2", "final_flux3", "update"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rt512_traffic.json")
-KERNEL_SYMBOL = {"trace_flux1": "k_trace_fused", "corner_final_update": "k_flux_fused"}
+KERNEL_SYMBOL = {"trace": "k_trace_fused", "flux_update": "k_flux_fused"}
 
 
 def source_hash():

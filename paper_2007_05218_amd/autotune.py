@@ -21,7 +21,7 @@ from . import hydro, inputs
 
 TBX = (8, 16, 32)
 TZS = (8, 16, 32, 64, 128)
-STAGES = ("trace_flux1", "corner_final_update")
+STAGES = ("trace", "flux_update")
 
 
 def shape_key(n):

@@ -96,14 +96,15 @@ __device__ __forceinline__ double ldb(const double *f, unsigned bo)
     return *(const double *)((const char *)f + bo);
 }
 
-__device__ __forceinline__ Face load_face_b(const WS &ws, int base, unsigned bo)
+// a traced state from fields f0 .. f0+4 of the column at offset lo of plane pp
+__device__ __forceinline__ Face load_face_b(const char *pp, unsigned lo, int f0)
 {
     Face f;
-    f.r = ldb(ws.f(base + 0), bo);
-    f.u = ldb(ws.f(base + 1), bo);
-    f.v = ldb(ws.f(base + 2), bo);
-    f.w = ldb(ws.f(base + 3), bo);
-    f.p = ldb(ws.f(base + 4), bo);
+    f.r = ws_ld(pp, lo, f0 + 0);
+    f.u = ws_ld(pp, lo, f0 + 1);
+    f.v = ws_ld(pp, lo, f0 + 2);
+    f.w = ws_ld(pp, lo, f0 + 3);
+    f.p = ws_ld(pp, lo, f0 + 4);
     f.ri = 0.0;
     return f;
 }
@@ -229,7 +230,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     const double fx2 = dt / (2.0 * g.dx[0]), fy2 = dt / (2.0 * g.dx[1]),
                  fz2 = dt / (2.0 * g.dx[2]);
     const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
-    const unsigned bsz = (unsigned)(g.s[0] * g.s[1]) * 8u;
+    const unsigned wo = ws.off(xc, yc);  // own column in the workspace
 
     // plane-to-plane carries (values of the previous plane)
     // (zero until the first plane has been processed; the values derived from
@@ -239,15 +240,15 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     int err = 0;
 
     for (int q = T.z0 - 1; q <= T.z1; ++q) {
-        const unsigned boc = (unsigned)cell(g, xc, yc, q) * 8u;
+        const char *pq = ws.plane(q);
         // (the (s|z) corner states of the warm-up plane use the round-1 z-flux
         // below it, which this segment does not have: the previous segment
         // covers them)
         const bool rz_c = inr(q, 0, n2 - 1) && q >= T.z0, rz_w = inr(q, -1, n2);
         // ---------------------------------------------------- loads
-        const Face qx_lo = load_face_b(ws, QLO(0, 0), boc), qx_hi = load_face_b(ws, QHI(0, 0), boc);
-        const Face qy_lo = load_face_b(ws, QLO(1, 0), boc), qy_hi = load_face_b(ws, QHI(1, 0), boc);
-        const Face qz_lo = load_face_b(ws, QLO(2, 0), boc), qz_hi = load_face_b(ws, QHI(2, 0), boc);
+        const Face qx_lo = load_face_b(pq, wo, QLO(0, 0)), qx_hi = load_face_b(pq, wo, QHI(0, 0));
+        const Face qy_lo = load_face_b(pq, wo, QLO(1, 0)), qy_hi = load_face_b(pq, wo, QHI(1, 0));
+        const Face qz_lo = load_face_b(pq, wo, QLO(2, 0)), qz_hi = load_face_b(pq, wo, QHI(2, 0));
         // ---------------------------------------------------- round-1 fluxes
         // through each lane's low x/y faces (the low neighbour's high state
         // comes through LDS) and through the plane's high z-face; the x/y
@@ -256,7 +257,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
         putF(xa.v, 0, t, qx_hi);
         putF(xa.v, 5, t, qy_hi);
         const Flux F1zn = hllc(with_ri(qz_hi),
-                               with_ri(load_face_b(ws, QLO(2, 0), boc + bsz)),  // next plane
+                               with_ri(load_face_b(ws.plane(q + 1), wo, QLO(2, 0))),  // next plane
                                2, gamma, igm1);
         __syncthreads();
         {
@@ -351,10 +352,10 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             const int p = q - 1;
             const bool pv = p >= T.z0;  // plane p is finished in this segment
             const bool rp_c = inr(p, 0, n2 - 1);
-            const unsigned bop = boc - bsz;
+            const char *pp = ws.plane(p);
             Face xl, xh, yl, yh;
             {
-                const Face a = load_face_b(ws, QLO(0, 0), bop), b = load_face_b(ws, QHI(0, 0), bop);
+                const Face a = load_face_b(pp, wo, QLO(0, 0)), b = load_face_b(pp, wo, QHI(0, 0));
                 const Flux dF2yz = getX(cz, 5, t);
                 xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
                 if (fb && pv && hD && hU && rx_f && ry_c && rp_c) err |= fb;
@@ -362,7 +363,7 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
                 if (fb && pv && hD && hU && rx_fh && ry_c && rp_c) err |= fb;
             }
             {
-                const Face a = load_face_b(ws, QLO(1, 0), bop), b = load_face_b(ws, QHI(1, 0), bop);
+                const Face a = load_face_b(pp, wo, QLO(1, 0)), b = load_face_b(pp, wo, QHI(1, 0));
                 const Flux dF2xz = getX(cz, 0, t);
                 yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
                 if (fb && pv && hL && hR && ry_f && rx_c && rp_c) err |= fb;

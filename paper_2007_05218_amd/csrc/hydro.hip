@@ -55,20 +55,17 @@ struct Geo {
 };
 
 // workspace fields: traced face states (direction d, high/low face,
-// component v), each a dense ghosted array like one state component
+// component v)
 __host__ __device__ constexpr int QHI(int d, int v) { return d * 10 + v; }
 __host__ __device__ constexpr int QLO(int d, int v) { return d * 10 + 5 + v; }
 constexpr int kFields = 30;
+constexpr int kXB = 16;  // cells of an x-block of the workspace
 
 // stages (block-count prefix arrays are kept per stage)
 enum { ST_FILL = 0, ST_DT = 1, ST_TRACE = 2, ST_FLUX = 3, ST_COUNT = 4 };
 constexpr int kDtCellsPerThread = 4;
 constexpr long long kDtMaxBlocks = 4096;
 
-__host__ __device__ __forceinline__ long long field_doubles(long long cs)
-{
-    return (cs + 31) / 32 * 32;
-}
 
 __device__ __forceinline__ long long cell(const Geo &g, int i, int j, int k)
 {
@@ -80,11 +77,46 @@ __device__ __forceinline__ long long stride(const Geo &g, int d)
     return d == 0 ? 1LL : (d == 1 ? (long long)g.s[0] : (long long)g.s[0] * g.s[1]);
 }
 
+// Workspace of one box: the traced face states of the cells x in [-1, n0],
+// y in [-1, n1], z in [-2, n2+1] (the traced region plus one plane on each
+// side that the flux kernel's first and last z-steps read and never use).
+// Plane by plane, row by row, each run of 16 cells of a row (x-block) keeps
+// its 30 fields together: field f of the run is the 16 doubles (one 128-byte
+// line) at f*128 bytes from the run's start.  A lane's 30 fields are then one
+// per-lane offset plus constant offsets from a per-plane base (no address
+// register per field), and the streams a kernel writes or reads at once are
+// neighbouring lines instead of 30 arrays a large power of two apart, which
+// land on the same memory channels.
+__host__ __device__ __forceinline__ int ws_xblocks(int n0) { return (n0 + 2 + kXB - 1) / kXB; }
+__host__ __device__ __forceinline__ long long ws_pitch(int n0, int n1)  // bytes per plane
+{
+    return (long long)(n1 + 2) * ws_xblocks(n0) * (kFields * kXB * 8);
+}
 struct WS {
-    double *base;
-    long long fs;  // doubles per field
-    __device__ __forceinline__ double *f(int idx) const { return base + idx * fs; }
+    char *base;        // plane z = -2
+    long long pitch;   // bytes per plane
+    int nxb;           // x-blocks per row
+    __device__ __forceinline__ const char *plane(int z) const
+    {
+        return base + (long long)(z + 2) * pitch;
+    }
+    // byte offset of column (x, y) within a plane
+    __device__ __forceinline__ unsigned off(int x, int y) const
+    {
+        const unsigned X = (unsigned)(x + 1);
+        return ((unsigned)(y + 1) * (unsigned)nxb + (X / kXB)) * (unsigned)(kFields * kXB * 8) +
+               (X % kXB) * 8u;
+    }
 };
+// field f of the column at byte offset lo of plane pointer pp
+__device__ __forceinline__ double ws_ld(const char *pp, unsigned lo, int f)
+{
+    return *(const double *)((pp + (size_t)lo) + f * (kXB * 8));
+}
+__device__ __forceinline__ void ws_st(const char *pp, unsigned lo, int f, double v)
+{
+    *(double *)((const_cast<char *>(pp) + (size_t)lo) + f * (kXB * 8)) = v;
+}
 
 struct Reg {
     int lo[3];
@@ -169,7 +201,7 @@ __device__ __forceinline__ Box1 resolve(const Launch &L)
         o.g = L.g;
         o.U = L.U;
         o.Un = L.Un;
-        o.ws.base = L.ws;
+        o.ws.base = (char *)L.ws;
         o.dt = L.dt;
         o.b = 0;
         o.blk = blockIdx.x;
@@ -187,12 +219,13 @@ __device__ __forceinline__ Box1 resolve(const Launch &L)
         o.g = L.geos[lo];
         o.U = L.Us ? L.Us[lo] : nullptr;
         o.Un = L.Uns ? L.Uns[lo] : nullptr;
-        o.ws.base = L.ws ? L.ws + L.wsoff[lo] : nullptr;
+        o.ws.base = L.ws ? (char *)(L.ws + L.wsoff[lo]) : nullptr;
         o.dt = L.dts ? L.dts + (long long)lo * L.dt_stride : nullptr;
         o.blk = x - L.pre[lo];
         o.nblk = L.pre[lo + 1] - L.pre[lo];
     }
-    o.ws.fs = field_doubles(o.g.cs);
+    o.ws.pitch = ws_pitch(o.g.n[0], o.g.n[1]);
+    o.ws.nxb = ws_xblocks(o.g.n[0]);
     return o;
 }
 
@@ -320,26 +353,6 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
     }
 }
 
-__device__ __forceinline__ Face load_face(const WS &ws, int base, long long o)
-{
-    Face f;
-    f.r = ws.f(base + 0)[o];
-    f.u = ws.f(base + 1)[o];
-    f.v = ws.f(base + 2)[o];
-    f.w = ws.f(base + 3)[o];
-    f.p = ws.f(base + 4)[o];
-    return f;
-}
-
-__device__ __forceinline__ void store_flux(const WS &ws, int base, long long o, const Flux &F)
-{
-    ws.f(base + 0)[o] = F.m;
-    ws.f(base + 1)[o] = F.mu;
-    ws.f(base + 2)[o] = F.mv;
-    ws.f(base + 3)[o] = F.mw;
-    ws.f(base + 4)[o] = F.e;
-}
-
 #include "flux_fused.h"
 #include "trace_fused.h"
 
@@ -361,8 +374,9 @@ bool box_valid(const hydro_box *b)
     }
     long long cs = 1;
     for (int d = 0; d < 3; ++d) cs *= (long long)b->n[d] + 2 * b->ng;
-    // the fused kernels address one component with 32-bit byte offsets
-    return cs < (1LL << 28);
+    // the fused kernels address one state component, and one workspace
+    // plane, with 32-bit byte offsets
+    return cs < (1LL << 28) && ws_pitch(b->n[0], b->n[1]) < (1LL << 31);
 }
 
 bool params_valid(const hydro_params *p)
@@ -416,7 +430,7 @@ Geo make_geo(const hydro_box *b)
 
 size_t box_ws_bytes(const Geo &g)
 {
-    size_t bytes = (size_t)kFields * (size_t)field_doubles(g.cs) * sizeof(double);
+    size_t bytes = (size_t)ws_pitch(g.n[0], g.n[1]) * (size_t)(g.n[2] + 4);
     return (bytes + 255) / 256 * 256;
 }
 
@@ -436,7 +450,7 @@ Launch single(const Geo &g, const double *U, double *Un, void *ws, const double 
 // ---------------------------------------------------------------- profiling hook
 
 enum { PG_FILL, PG_DT, PG_TRACE, PG_FUSED, PG_COUNT };
-const char *const kPgNames[PG_COUNT] = {"fill", "dt", "trace_flux1", "corner_final_update"};
+const char *const kPgNames[PG_COUNT] = {"fill", "dt", "trace", "flux_update"};
 hipEvent_t g_ev[2 * PG_COUNT];
 bool g_ev_on = false;
 

@@ -27,19 +27,14 @@ constexpr int kTPlane = 432;  // LDS cells of one plane: (BX+4)(BY+4) <= 432 for
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// stores of five components at a 32-bit byte offset from uniform field bases
-__device__ __forceinline__ void st5(const WS &ws, int base, unsigned bo, double a0, double a1,
-                                    double a2, double a3, double a4)
+// a traced state into fields f0 .. f0+4 of the column at offset lo of plane pp
+__device__ __forceinline__ void stb(const char *pp, unsigned lo, int f0, const Face &f)
 {
-    *(double *)((char *)ws.f(base + 0) + bo) = a0;
-    *(double *)((char *)ws.f(base + 1) + bo) = a1;
-    *(double *)((char *)ws.f(base + 2) + bo) = a2;
-    *(double *)((char *)ws.f(base + 3) + bo) = a3;
-    *(double *)((char *)ws.f(base + 4) + bo) = a4;
-}
-__device__ __forceinline__ void stb(const WS &ws, int base, unsigned bo, const Face &f)
-{
-    st5(ws, base, bo, f.r, f.u, f.v, f.w, f.p);
+    ws_st(pp, lo, f0 + 0, f.r);
+    ws_st(pp, lo, f0 + 1, f.u);
+    ws_st(pp, lo, f0 + 2, f.v);
+    ws_st(pp, lo, f0 + 3, f.w);
+    ws_st(pp, lo, f0 + 4, f.p);
 }
 
 __global__ void __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(3)))
@@ -72,6 +67,7 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     const int x = x0 + tx, y = y0 + ty;  // this thread's column
     const bool inner = x <= n0 && y <= n1;
     const int rc = (ty + 2) * RW + (tx + 2);  // own column in the plane buffer
+    const unsigned wo = ws.off(inner ? x : n0, inner ? y : n1);  // own column in the workspace
 
     const double dt = *o.dt;
     const double dtdx = dt / g.dx[0], dtdy = dt / g.dx[1], dtdz = dt / g.dx[2];
@@ -158,15 +154,15 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         const double c = sound_ri(gamma, wp[2], ri);
         const int slot = (p + 6) % 3;
         Face hi, lo;
-        const unsigned bo = (unsigned)cell(g, inner ? x : n0, inner ? y : n1, p) * 8u;
+        const char *pp = ws.plane(p);
         // ------------------------------------------------ z trace
         trace_cell(wr, ww, wu, wv, wp, c, ri, 2, dtdz, hi, lo);
         if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
         if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
         if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
         if (inner) {
-            stb(ws, QHI(2, 0), bo, hi);
-            stb(ws, QLO(2, 0), bo, lo);
+            stb(pp, wo, QHI(2, 0), hi);
+            stb(pp, wo, QLO(2, 0), lo);
         }
         // ------------------------------------------------ x and y traces of plane p
         {
@@ -186,8 +182,8 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
         if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
         if (inner) {
-            stb(ws, QHI(0, 0), bo, hi);
-            stb(ws, QLO(0, 0), bo, lo);
+            stb(pp, wo, QHI(0, 0), hi);
+            stb(pp, wo, QLO(0, 0), lo);
         }
         {
             double rs[5], a1[5], a2[5], a3[5], ps[5];
@@ -206,8 +202,8 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
         if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
         if (inner) {
-            stb(ws, QHI(1, 0), bo, hi);
-            stb(ws, QLO(1, 0), bo, lo);
+            stb(pp, wo, QHI(1, 0), hi);
+            stb(pp, wo, QLO(1, 0), lo);
         }
         __syncthreads();
     }

@@ -39,8 +39,9 @@ def test_state_and_workspace_sizes():
     U, box, prm = inputs.sod(32)
     assert hydro.state_elems(box) == U.size == 5 * 40 ** 3
     ws = hydro.workspace_bytes(box)
-    # the traced face states: 3 directions x 2 faces x 5 components
-    assert ws >= 30 * 40 ** 3 * 8 and ws % 256 == 0
+    # the traced face states (3 directions x 2 faces x 5 components) of the
+    # traced region, one cell beyond the 32^3 valid cells
+    assert ws >= 30 * 34 ** 3 * 8 and ws % 256 == 0
     boxes = [inputs.box_desc((16, 32, 64)), inputs.box_desc((64, 16, 16))]
     assert hydro.workspace_bytes(boxes) == sum(hydro.workspace_bytes(b) for b in boxes)
 
@@ -50,6 +51,8 @@ def test_state_and_workspace_sizes():
     dict(n=(3, 8, 8), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0)),  # periodic axis shorter than ng
     dict(bc_lo=(0, 1, 1), bc_hi=(1, 1, 1)),               # unpaired periodic
     dict(bc_lo=(5, 1, 1), bc_hi=(5, 1, 1)),
+    dict(n=(6000, 12000, 1)),  # a component beyond 32-bit byte offsets
+    dict(n=(3000, 3000, 1)),   # a workspace plane beyond 32-bit byte offsets
 ])
 def test_invalid_boxes_rejected(bad):
     d = inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1))
