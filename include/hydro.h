@@ -143,9 +143,12 @@ hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
                            void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream);
 
 /* Plan for a fixed list of boxes: validates them, chooses the tile shapes
- * (autotune_json: NULL for the built-in table, else a JSON object mapping
- * shape classes to tiles as written by the package's autotuner) and builds
- * the device work list.  *plan receives an opaque handle. */
+ * (autotune_json: NULL for the built-in choice, else a JSON object mapping
+ * box shapes "NXxNYxNZ" to [tbx, tzs] for both fused kernels or
+ * [tbx1, tzs1, tbx2, tzs2] for the trace and flux kernels, tbx in {8,16,32},
+ * tzs >= 1, a pair 0, 0 keeping that kernel's built-in tile; as written by
+ * the package's autotuner) and builds the device work list.  *plan receives
+ * an opaque handle.  HYDRO_EINVAL for an invalid box or table. */
 hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,
                                void **plan);
 void hydro_plan_destroy(void *plan);

@@ -39,17 +39,22 @@ def candidates(n):
     return [(b, z) for b in TBX for z in zs]
 
 
+BUILTIN = (0, 0)  # table entry keeping a kernel's built-in tile
+MARGIN = 0.03     # a tuned tile must beat the built-in one by this fraction
+
+
 def _time_class(n, tiles, prm, nboxes, reps, torch):
-    """{tile: (trace-kernel ms, flux-kernel ms)} for a batch of boxes of shape n."""
-    states, boxes = [], []
-    for i in range(nboxes):
-        U, box, _ = inputs.smooth(n, seed=1000 + i, dx=(1.0 / 64,) * 3)
-        states.append(U)
-        boxes.append(box)
+    """{tile: (trace-kernel ms, flux-kernel ms)} for a batch of boxes of shape
+    n; the tile BUILTIN times the library's built-in choice."""
+    # a few distinct synthetic states, repeated to fill the batch
+    distinct = [inputs.smooth(n, seed=1000 + i, dx=(1.0 / 64,) * 3)[:2]
+                for i in range(min(nboxes, 8))]
+    states = [distinct[i % len(distinct)][0] for i in range(nboxes)]
+    boxes = [distinct[i % len(distinct)][1] for i in range(nboxes)]
     out = {}
     for tb in tiles:
         lev = hydro.Level(states, boxes, prm, shared_dt=True,
-                          autotune_json=table_json({shape_key(n): tb}))
+                          autotune_json=None if tb == BUILTIN else table_json({shape_key(n): tb}))
         lev.step()  # warm-up (and first touch of the workspace)
         torch.cuda.synchronize()
         timer = hydro.StageTimer()
@@ -61,12 +66,25 @@ def _time_class(n, tiles, prm, nboxes, reps, torch):
     return out
 
 
-def tune(boxes, prm=None, max_boxes_per_class=64, min_cells_per_class=2 ** 21, reps=3,
+def _pick(t, kernel):
+    """The fastest tile for one kernel (0: trace, 1: flux), kept only if it
+    beats the built-in choice by MARGIN (timing noise must not replace a good
+    built-in tile with an equal one)."""
+    best = min(t, key=lambda k: t[k][kernel])
+    if best != BUILTIN and t[best][kernel] < (1.0 - MARGIN) * t[BUILTIN][kernel]:
+        return best
+    return BUILTIN
+
+
+def tune(boxes, prm=None, max_boxes_per_class=4096, min_cells_per_class=2 ** 23, reps=3,
          log=None):
     """Tune every box shape of ``boxes``.  Each class is timed on a batch of
-    synthetic boxes of that shape (enough boxes to fill the GPU, at most
-    ``max_boxes_per_class``); the trace and flux kernels each get their
-    fastest tile.  Returns ({shape: (tbx1, tzs1, tbx2, tzs2)}, timings)."""
+    synthetic boxes of that shape (enough boxes to keep the GPU saturated, as
+    a level's launch does: at least ``min_cells_per_class`` cells, at most
+    ``max_boxes_per_class`` boxes) with the built-in tiles and every candidate; the
+    trace and flux kernels each get their fastest tile when it beats the
+    built-in one by MARGIN.  Returns ({shape: (tbx1, tzs1, tbx2, tzs2)} for
+    the shapes where a kernel changed (0, 0 = built-in), timings)."""
     import torch
     prm = prm or inputs.params_desc()
     shapes = sorted({tuple(b["n"]) for b in boxes})
@@ -74,12 +92,13 @@ def tune(boxes, prm=None, max_boxes_per_class=64, min_cells_per_class=2 ** 21, r
     for n in shapes:
         cells = n[0] * n[1] * n[2]
         nb = max(1, min(max_boxes_per_class, -(-min_cells_per_class // cells)))
-        t = _time_class(n, candidates(n), prm, nb, reps, torch)
-        b1 = min(t, key=lambda k: t[k][0])
-        b2 = min(t, key=lambda k: t[k][1])
-        table[shape_key(n)] = (b1[0], b1[1], b2[0], b2[1])
+        t = _time_class(n, [BUILTIN] + candidates(n), prm, nb, reps, torch)
+        b1, b2 = _pick(t, 0), _pick(t, 1)
+        if (b1, b2) != (BUILTIN, BUILTIN):
+            table[shape_key(n)] = (b1[0], b1[1], b2[0], b2[1])
         timings[shape_key(n)] = {"%d,%d" % k: v for k, v in t.items()}
         if log:
-            log("tiles %s: trace %s (%.3f ms), flux %s (%.3f ms), %d boxes"
-                % (shape_key(n), b1, t[b1][0], b2, t[b2][1], nb))
+            log("tiles %s: trace %s (%.3f ms, built-in %.3f), flux %s (%.3f ms, built-in %.3f), "
+                "%d boxes" % (shape_key(n), b1, t[b1][0], t[BUILTIN][0], b2, t[b2][1],
+                              t[BUILTIN][1], nb))
     return table, timings

@@ -354,8 +354,15 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
             const bool rp_c = inr(p, 0, n2 - 1);
             const char *pp = ws.plane(p);
             Face xl, xh, yl, yh;
+            // (lanes whose final x or y states are never used skip reading
+            // their traced states: the ring rows for x, the ring columns for y,
+            // and every lane in a segment's warm-up plane)
             {
-                const Face a = load_face_b(pp, wo, QLO(0, 0)), b = load_face_b(pp, wo, QHI(0, 0));
+                Face a = {}, b = {};
+                if (pv && hD && hU) {
+                    a = load_face_b(pp, wo, QLO(0, 0));
+                    b = load_face_b(pp, wo, QHI(0, 0));
+                }
                 const Flux dF2yz = getX(cz, 5, t);
                 xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
                 if (fb && pv && hD && hU && rx_f && ry_c && rp_c) err |= fb;
@@ -363,7 +370,11 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
                 if (fb && pv && hD && hU && rx_fh && ry_c && rp_c) err |= fb;
             }
             {
-                const Face a = load_face_b(pp, wo, QLO(1, 0)), b = load_face_b(pp, wo, QHI(1, 0));
+                Face a = {}, b = {};
+                if (pv && hL && hR) {
+                    a = load_face_b(pp, wo, QLO(1, 0));
+                    b = load_face_b(pp, wo, QHI(1, 0));
+                }
                 const Flux dF2xz = getX(cz, 0, t);
                 yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
                 if (fb && pv && hL && hR && ry_f && rx_c && rp_c) err |= fb;

@@ -386,28 +386,26 @@ bool params_valid(const hydro_params *p)
 }
 
 // Built-in tile choice for the fused kernels when no tuned table applies
-// (from a sweep on the 512^3 and 256^3 boxes): the trace kernel prefers wide
-// tiles (32 x 8 columns) and the flux kernel square ones (16 x 16); both
-// prefer z-segments of 16-32 planes, which expose more blocks and keep the
-// planes in flight in cache; a segment costs one (trace) or two (flux) extra
-// warm-up planes.
-int default_zs(long long tiles, int nz)
+// (from a sweep on the 512^3 box): both kernels prefer square tiles
+// (16 x 16 columns); the trace kernel z-segments of 16-32 planes (more
+// blocks, planes in flight kept in cache), the flux kernel up to 64 planes
+// (a segment costs it two warm-up planes).
+int default_zs(long long tiles, int nz, int zmax)
 {
     long long nzs = (8192 + tiles - 1) / tiles;  // aim at >= 8192 blocks (32 per CU)
     int zs = (int)((nz + nzs - 1) / nzs);
     if (zs < 16) zs = 16;
-    if (zs > 32) zs = 32;
+    if (zs > zmax) zs = zmax;
     return zs;
 }
 
 void set_default_tiles(Geo &g)
 {
-    g.tbx1 = g.n[0] + 2 >= 62 ? 32 : 16;
-    const int t1x = g.tbx1, t1y = 256 / g.tbx1;
-    g.tzs1 = default_zs((long long)((g.n[0] + 2 + t1x - 1) / t1x) * ((g.n[1] + 2 + t1y - 1) / t1y),
-                        g.n[2] + 2);
+    g.tbx1 = 16;
+    g.tzs1 = default_zs((long long)((g.n[0] + 2 + 15) / 16) * ((g.n[1] + 2 + 15) / 16),
+                        g.n[2] + 2, 32);
     g.tbx2 = 16;
-    g.tzs2 = default_zs((long long)((g.n[0] + 13) / 14) * ((g.n[1] + 13) / 14), g.n[2]);
+    g.tzs2 = default_zs((long long)((g.n[0] + 13) / 14) * ((g.n[1] + 13) / 14), g.n[2], 64);
 }
 
 bool tiles_valid(int tbx, int tzs) { return (tbx == 8 || tbx == 16 || tbx == 32) && tzs >= 1; }
@@ -489,8 +487,9 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
 
 // A tuned tile table: a flat JSON object mapping a box shape "NXxNYxNZ" to
 // [tbx, tzs] (tile width in columns, z-segment length; both kernels) or
-// [tbx1, tzs1, tbx2, tzs2] (trace kernel, flux kernel), e.g.
-//   {"16x32x64": [16, 32], "64x64x64": [32, 64, 16, 64]}
+// [tbx1, tzs1, tbx2, tzs2] (trace kernel, flux kernel), where a pair 0, 0
+// keeps that kernel's built-in tile, e.g.
+//   {"16x32x64": [16, 32], "64x64x64": [32, 64, 0, 0]}
 // as written by the package's autotuner.  Shapes not listed keep the
 // built-in choice.  Returns false on a syntax error or an invalid tile.
 struct TileRule {
@@ -547,7 +546,9 @@ bool parse_tiles(const char *js, std::vector<TileRule> &out)
         } else if (k != 4) {
             return false;
         }
-        if (!tiles_valid(r.t[0], r.t[1]) || !tiles_valid(r.t[2], r.t[3])) return false;
+        for (int kk = 0; kk < 4; kk += 2)
+            if (!(r.t[kk] == 0 && r.t[kk + 1] == 0) && !tiles_valid(r.t[kk], r.t[kk + 1]))
+                return false;
         out.push_back(r);
         ws();
         if (*c == ',') {
@@ -668,10 +669,14 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
         Geo g = make_geo(&boxes[b]);
         for (const TileRule &r : rules)
             if (r.n[0] == g.n[0] && r.n[1] == g.n[1] && r.n[2] == g.n[2]) {
-                g.tbx1 = r.t[0];
-                g.tzs1 = r.t[1];
-                g.tbx2 = r.t[2];
-                g.tzs2 = r.t[3];
+                if (r.t[0] != 0) {
+                    g.tbx1 = r.t[0];
+                    g.tzs1 = r.t[1];
+                }
+                if (r.t[2] != 0) {
+                    g.tbx2 = r.t[2];
+                    g.tzs2 = r.t[3];
+                }
             }
         P->geos.push_back(g);
         wsoff[b] = (long long)(P->ws_bytes / sizeof(double));

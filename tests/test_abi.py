@@ -115,7 +115,8 @@ def test_status_strings():
 @pytest.mark.parametrize("js", ['{"16x16x16": [12, 8]}', '{"16x16x16": [16, 0]}', '{16x16x16: [16, 8]}',
                                 '{"16x16": [16, 8]}', '["16x16x16"]', '{"16x16x16": [16, 8]} x',
                                 '{"16x16x16": [16, 8, 32]}', '{"16x16x16": [16, 8, 32, 8, 8]}',
-                                '{"16x16x16": [16, 8, 24, 8]}'])
+                                '{"16x16x16": [16, 8, 24, 8]}', '{"16x16x16": [16, 8, 0, 8]}',
+                                '{"16x16x16": [0, 4, 16, 8]}'])
 def test_plan_rejects_bad_tile_tables(js):
     # the table is parsed before any device allocation, so this needs no GPU
     L = hydro.lib()

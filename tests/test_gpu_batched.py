@@ -117,7 +117,11 @@ def test_autotuner_runs(gpu):
     boxes = [inputs.box_desc((16, 32, 16)), inputs.box_desc((32, 16, 64))]
     table, timings = autotune.tune(boxes, max_boxes_per_class=4, min_cells_per_class=1,
                                    reps=1)
-    assert set(table) == {"16x32x16", "32x16x64"}
+    assert set(timings) == {"16x32x16", "32x16x64"} and set(table) <= set(timings)
     for k, (tbx1, tzs1, tbx2, tzs2) in table.items():
-        assert tbx1 in (8, 16, 32) and tzs1 >= 1 and tbx2 in (8, 16, 32) and tzs2 >= 1
+        for tbx, tzs in ((tbx1, tzs1), (tbx2, tzs2)):
+            assert (tbx, tzs) == autotune.BUILTIN or (tbx in (8, 16, 32) and tzs >= 1)
+        assert (tbx1, tzs1, tbx2, tzs2) != autotune.BUILTIN * 2
     gpu.Plan(boxes, autotune.table_json(table)).close()
+    # a table keeping one kernel's built-in tile is accepted
+    gpu.Plan(boxes, autotune.table_json({"16x32x16": (16, 8) + autotune.BUILTIN})).close()

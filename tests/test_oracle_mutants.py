@@ -49,6 +49,9 @@ MUTANTS = {
     "minmod-like slope bound": (
         "return copysign(mn(mn(fabs(dc), 2.0 * fabs(dl)), 2.0 * fabs(dr)), dc);",
         "return copysign(mn(mn(fabs(dc), fabs(dl)), 2.0 * fabs(dr)), dc);"),
+    "HLLC star energy pressure-work sign": (
+        "Us[4] = chi * (E + (rho * (Ss - uK)) * (Ss + pK / (rho * (SK - uK))));",
+        "Us[4] = chi * (E + (rho * (Ss - uK)) * (Ss - pK / (rho * (SK - uK))));"),
     "HLLC star normal momentum": (
         "Us[1 + d] = chi * (rho * Ss);",
         "Us[1 + d] = chi * (rho * uK);"),
