@@ -139,8 +139,11 @@ def time_level(hydro, torch, inputs, steps, warmup):
     cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in boxes)
     t0 = time.perf_counter()
     table, _ = autotune.tune(boxes, prm, log=log)
+    table, ms_b, ms_t = autotune.validate(states, boxes, prm, table)
+    log("tile table validated on the level: built-in %s ms, tuned %s ms per step -> %s"
+        % (ms_b, ms_t, "tuned" if table else "built-in"))
     tune_s = time.perf_counter() - t0
-    js = autotune.table_json(table)
+    js = autotune.table_json(table) if table else None
     ms_default = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup)
     ms_batched = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup, js)
     # the same boxes, one library call per box and stage (one stream)

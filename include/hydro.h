@@ -116,10 +116,16 @@ hydro_status estimate_dt(double *U_dev, const hydro_box *box, const hydro_params
  * does it).  Ghost cells of U_new_dev are not written.  U_new_dev must not
  * overlap U_dev.  ws_dev must hold hydro_workspace_bytes(box, 1) bytes
  * (HYDRO_ENOWS otherwise), aligned to 256 bytes; its contents on entry do
- * not matter.  Error bits go to *err_dev (not cleared by the call). */
+ * not matter.  Error bits go to *err_dev (not cleared by the call).
+ * If dt_next_dev is not NULL it receives the CFL timestep of the new state,
+ * bitwise what estimate_dt gives for U_new_dev (its valid cells decide it),
+ * reduced in the update's epilogue instead of a separate pass over U_new:
+ * a stepping loop then needs only hydro_fill_ghosts before the next
+ * advance_box.  It must not overlap *dt_dev (HYDRO_EINVAL).  With a
+ * non-finite new state the value is unspecified (error bit 1 is raised). */
 hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box *box,
-                         const hydro_params *prm, const double *dt_dev, void *ws_dev,
-                         size_t ws_bytes, int32_t *err_dev, void *stream);
+                         const hydro_params *prm, const double *dt_dev, double *dt_next_dev,
+                         void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream);
 
 /* Batched timestep over a list of boxes (a level of Sec. II's MultiFab):
  * fills the ghosts of every box, writes each box's dt to dt_dev[b] and, if
@@ -136,11 +142,22 @@ hydro_status estimate_dt_boxes(int nb, double *const *U_ptrs_dev, const void *pl
  * (dt_stride = 1) or by one shared timestep dt_dev[0] (dt_stride = 0), with
  * one launch per stage for all boxes together.  Every box's result is
  * bitwise the one advance_box gives it.  ws_dev must hold
- * hydro_workspace_bytes(boxes, nb) bytes. */
+ * hydro_workspace_bytes(boxes, nb) bytes.  If dt_next_dev is not NULL,
+ * dt_next_dev[b] receives box b's next timestep as advance_box's dt_next_dev
+ * does, and, if dt_next_min_dev is not NULL too, *dt_next_min_dev the
+ * minimum over boxes (bitwise what estimate_dt_boxes gives for the new
+ * states); neither may overlap the timesteps in use or each other. */
 hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
                            double *const *U_new_ptrs_dev, const void *plan,
                            const hydro_params *prm, const double *dt_dev, int dt_stride,
-                           void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream);
+                           double *dt_next_dev, double *dt_next_min_dev, void *ws_dev,
+                           size_t ws_bytes, int32_t *err_dev, void *stream);
+
+/* Ghost fill of every box of `plan` (hydro_fill_ghosts per box, one launch):
+ * with the timesteps advance_boxes reduced, a batched stepping loop is
+ * hydro_fill_ghosts_boxes + advance_boxes. */
+hydro_status hydro_fill_ghosts_boxes(int nb, double *const *U_ptrs_dev, const void *plan,
+                                     void *stream);
 
 /* Plan for a fixed list of boxes: validates them, chooses the tile shapes
  * (autotune_json: NULL for the built-in choice, else a JSON object mapping

@@ -102,3 +102,31 @@ def tune(boxes, prm=None, max_boxes_per_class=4096, min_cells_per_class=2 ** 23,
                 "%d boxes" % (shape_key(n), b1, t[b1][0], t[BUILTIN][0], b2, t[b2][1],
                               t[BUILTIN][1], nb))
     return table, timings
+
+
+def validate(states, boxes, prm, table, steps=4, rounds=3):
+    """Time the whole level with the built-in tiles and with ``table``
+    (alternating, ``rounds`` times ``steps`` steps each) and keep the table
+    only if the level is faster with it: per-class timings need not add up
+    to the level's (its classes share the GPU in one launch).  Returns
+    (table or {}, ms per step built-in, ms per step with the table)."""
+    import torch
+    if not table:
+        return {}, None, None
+    levels = [hydro.Level(states, boxes, prm, shared_dt=True),
+              hydro.Level(states, boxes, prm, shared_dt=True, autotune_json=table_json(table))]
+    best = [float("inf"), float("inf")]
+    for lev in levels:
+        lev.step()
+    for _ in range(rounds):
+        for i, lev in enumerate(levels):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lev.run(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            best[i] = min(best[i], e0.elapsed_time(e1) / steps)
+    del levels
+    torch.cuda.empty_cache()
+    return (table if best[1] < best[0] else {}), best[0], best[1]

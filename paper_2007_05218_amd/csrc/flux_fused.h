@@ -192,7 +192,7 @@ __host__ inline long long fused_blocks(const Geo &g)
 #define HYDRO_FUSED_WAVES 2
 #endif
 __global__ void __launch_bounds__(kFT) __attribute__((amdgpu_waves_per_eu(HYDRO_FUSED_WAVES)))
-k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_dev)
+k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz, int *err_dev)
 {
     __shared__ XBuf xa, xb;
     // own-lane carries: dF2xz, dF2yz, F3z of the previous plane, F1z through
@@ -238,6 +238,8 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
     Face c_zx_hi = {}, c_zy_hi = {}, fz_hi = {};  // corner (z|x), (z|y), final z: high face
     Flux F2zx = {}, F2zy = {};    // (z|x), (z|y) fluxes through the plane's low z-face
     int err = 0;
+    // CFL bound of the lane's new cells, for the next step's timestep
+    double dtn = __longlong_as_double((long long)kInfBits);
 
     for (int q = T.z0 - 1; q <= T.z1; ++q) {
         const char *pq = ws.plane(q);
@@ -431,12 +433,15 @@ k_flux_fused(Launch L, double gamma, double gx, double gy, double gz, int *err_d
                 }
                 if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
                 if (qn.p <= 0.0) err |= HYDRO_ERR_P;
+                if (o.dtn) dtn = dmin(dtn, cfl_cell(qn, gamma, g.dx));
             }
             putX(cz, 10, t, F3zq);
             __syncthreads();
         }
     }
     if (err) atomicOr(err_dev, err);
+    // (the z-march ended on a barrier: the exchange buffers are free)
+    if (o.dtn) block_dt_min(dtn, cfl, o.dtn, L.dtn_min, xa.v[0]);
 }
 
 }  // namespace

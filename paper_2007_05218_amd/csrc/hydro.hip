@@ -41,6 +41,7 @@ using namespace hydro;
 namespace {
 
 constexpr int kBlock = 256;
+constexpr unsigned long long kInfBits = 0x7FF0000000000000ULL;  // +inf as a bit pattern
 
 struct Geo {
     int n[3];
@@ -181,6 +182,10 @@ struct Launch {
     const long long *wsoff;  // doubles from the workspace base
     const double *dts;
     int dt_stride;
+    // optional: the CFL timestep of the new state, reduced by the flux kernel
+    // (per box, as 64-bit patterns for atomicMin) and the minimum over boxes
+    unsigned long long *dtn;
+    unsigned long long *dtn_min;
 };
 
 struct Box1 {
@@ -192,6 +197,7 @@ struct Box1 {
     int b;            // box index within the batch (0 for a single box)
     long long blk;    // block index within the box
     long long nblk;   // blocks of this box in this stage
+    unsigned long long *dtn;  // this box's next-step timestep (bit pattern), or null
 };
 
 __device__ __forceinline__ Box1 resolve(const Launch &L)
@@ -224,6 +230,7 @@ __device__ __forceinline__ Box1 resolve(const Launch &L)
         o.blk = x - L.pre[lo];
         o.nblk = L.pre[lo + 1] - L.pre[lo];
     }
+    o.dtn = L.dtn ? L.dtn + o.b : nullptr;
     o.ws.pitch = ws_pitch(o.g.n[0], o.g.n[1]);
     o.ws.nxb = ws_xblocks(o.g.n[0]);
     return o;
@@ -260,8 +267,8 @@ __global__ void __launch_bounds__(kBlock) k_fill(Launch L, unsigned long long *d
     double *U = const_cast<double *>(o.U);
     long long t = o.blk * kBlock + threadIdx.x;
     if (t == 0) {
-        if (dt_bits) dt_bits[o.b] = 0x7FF0000000000000ULL;
-        if (dtmin_bits && o.b == 0) *dtmin_bits = 0x7FF0000000000000ULL;
+        if (dt_bits) dt_bits[o.b] = kInfBits;
+        if (dtmin_bits && o.b == 0) *dtmin_bits = kInfBits;
     }
     const long long s0 = g.s[0], s1 = g.s[1];
     const long long ng2 = 2LL * g.ng;
@@ -313,6 +320,38 @@ __device__ __forceinline__ double wave_min(double v)
     return v;
 }
 
+// the CFL bound of one cell: min_d dx_d / (|u_d| + c)
+__device__ __forceinline__ double cfl_cell(const Prim &q, double gamma, const double (&dx)[3])
+{
+    double c = sound_ri(gamma, q.p, q.ri);
+    double a = dx[0] / (fabs(q.u) + c);
+    double b = dx[1] / (fabs(q.v) + c);
+    double e = dx[2] / (fabs(q.w) + c);
+    return dmin(dmin(a, b), e);
+}
+
+// cfl times the minimum of m over a 256-thread block, atomically min-ed into
+// *box_bits and (if not null) *min_bits as 64-bit patterns (positive doubles
+// order like their bit patterns).  fl(cfl*x) is monotone in x, so the min of
+// the scaled block minima is the scaled global minimum, bit for bit, in any
+// order.  Every thread of the block must call it; part is LDS scratch for
+// kBlock/64 doubles that no thread uses meanwhile.
+__device__ __forceinline__ void block_dt_min(double m, double cfl, unsigned long long *box_bits,
+                                             unsigned long long *min_bits, double *part)
+{
+    m = wave_min(m);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = part[0];
+        for (int w = 1; w < kBlock / 64; ++w) b = dmin(b, part[w]);
+        unsigned long long v = (unsigned long long)__double_as_longlong(cfl * b);
+        atomicMin(box_bits, v);
+        if (min_bits) atomicMin(min_bits, v);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cfl,
                                                unsigned long long *dt_bits,
                                                unsigned long long *dtmin_bits)
@@ -322,7 +361,7 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
     const double *U = o.U;
     const double gm1 = gamma - 1.0;
     const long long nvalid = (long long)g.n[0] * g.n[1] * g.n[2];
-    double m = __longlong_as_double(0x7FF0000000000000LL);
+    double m = __longlong_as_double((long long)kInfBits);
     for (long long t = o.blk * kBlock + threadIdx.x; t < nvalid; t += o.nblk * kBlock) {
         int i = (int)(t % g.n[0]);
         long long r = t / g.n[0];
@@ -331,26 +370,10 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
         long long c0 = cell(g, i, j, k);
         Prim q = prim_of(U[c0], U[g.cs + c0], U[2 * g.cs + c0], U[3 * g.cs + c0],
                          U[4 * g.cs + c0], gm1);
-        double c = sound_ri(gamma, q.p, q.ri);
-        double a = g.dx[0] / (fabs(q.u) + c);
-        double b = g.dx[1] / (fabs(q.v) + c);
-        double e = g.dx[2] / (fabs(q.w) + c);
-        m = dmin(m, dmin(dmin(a, b), e));
+        m = dmin(m, cfl_cell(q, gamma, g.dx));
     }
-    m = wave_min(m);
     __shared__ double part[kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) part[wid] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = part[0];
-        for (int w = 1; w < kBlock / 64; ++w) b = dmin(b, part[w]);
-        // fl(cfl*x) is monotone in x, so the min of the scaled block minima
-        // is the scaled global minimum, bit for bit
-        unsigned long long v = (unsigned long long)__double_as_longlong(cfl * b);
-        atomicMin(dt_bits + o.b, v);
-        if (dtmin_bits) atomicMin(dtmin_bits, v);
-    }
+    block_dt_min(m, cfl, dt_bits + o.b, dtmin_bits, part);
 }
 
 #include "flux_fused.h"
@@ -477,8 +500,8 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
                        prm->grav[1], prm->grav[2]);
     prof(PG_TRACE, 1, st);
     prof(PG_FUSED, 0, st);
-    hipLaunchKernelGGL(k_flux_fused, set(ST_FLUX), dim3(kFT), 0, st, L, gamma, prm->grav[0],
-                       prm->grav[1], prm->grav[2], err_dev);
+    hipLaunchKernelGGL(k_flux_fused, set(ST_FLUX), dim3(kFT), 0, st, L, gamma, prm->cfl,
+                       prm->grav[0], prm->grav[1], prm->grav[2], err_dev);
     prof(PG_FUSED, 1, st);
     return launch_status();
 }
@@ -600,10 +623,12 @@ hydro_status hydro_fill_ghosts(double *U_dev, const hydro_box *box, void *stream
 {
     if (!U_dev || !box_valid(box)) return HYDRO_EINVAL;
     Geo g = make_geo(box);
+    hipStream_t st = (hipStream_t)stream;
     Launch L = single(g, U_dev, nullptr, nullptr, nullptr);
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)stage_blocks(g, ST_FILL)), dim3(kBlock), 0,
-                       (hipStream_t)stream, L, (unsigned long long *)nullptr,
-                       (unsigned long long *)nullptr);
+    prof(PG_FILL, 0, st);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)stage_blocks(g, ST_FILL)), dim3(kBlock), 0, st,
+                       L, (unsigned long long *)nullptr, (unsigned long long *)nullptr);
+    prof(PG_FILL, 1, st);
     return launch_status();
 }
 
@@ -626,12 +651,21 @@ hydro_status estimate_dt(double *U_dev, const hydro_box *box, const hydro_params
     return launch_status();
 }
 
+// byte ranges [a, a+na) and [b, b+nb) overlap
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
 hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box *box,
-                         const hydro_params *prm, const double *dt_dev, void *ws_dev,
-                         size_t ws_bytes, int32_t *err_dev, void *stream)
+                         const hydro_params *prm, const double *dt_dev, double *dt_next_dev,
+                         void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream)
 {
     if (!U_dev || !U_new_dev || !dt_dev || !ws_dev || !err_dev || !box_valid(box) ||
         !params_valid(prm))
+        return HYDRO_EINVAL;
+    if (dt_next_dev && overlaps(dt_next_dev, sizeof(double), dt_dev, sizeof(double)))
         return HYDRO_EINVAL;
     if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
     Geo g = make_geo(box);
@@ -644,6 +678,7 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
     long long grid[ST_COUNT];
     for (int s = 0; s < ST_COUNT; ++s) grid[s] = stage_blocks(g, s);
     Launch L = single(g, U_dev, U_new_dev, ws_dev, dt_dev);
+    L.dtn = (unsigned long long *)dt_next_dev;
     return enqueue_advance(L, grid, nullptr, prm, err_dev, (hipStream_t)stream);
 }
 
@@ -768,17 +803,44 @@ hydro_status estimate_dt_boxes(int nb, double *const *U_ptrs_dev, const void *pl
 hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
                            double *const *U_new_ptrs_dev, const void *plan,
                            const hydro_params *prm, const double *dt_dev, int dt_stride,
-                           void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream)
+                           double *dt_next_dev, double *dt_next_min_dev, void *ws_dev,
+                           size_t ws_bytes, int32_t *err_dev, void *stream)
 {
     const Plan *P = (const Plan *)plan;
     if (!P || nb != P->nb || !U_ptrs_dev || !U_new_ptrs_dev || !dt_dev || !ws_dev ||
-        !err_dev || !params_valid(prm) || (dt_stride != 0 && dt_stride != 1))
+        !err_dev || !params_valid(prm) || (dt_stride != 0 && dt_stride != 1) ||
+        (dt_next_min_dev && !dt_next_dev))
         return HYDRO_EINVAL;
+    {  // the next-step timesteps must not overlap the ones in use or each other
+        const size_t ndt = (dt_stride ? (size_t)nb : 1) * sizeof(double);
+        const size_t nn = (size_t)nb * sizeof(double);
+        if (dt_next_dev && overlaps(dt_next_dev, nn, dt_dev, ndt)) return HYDRO_EINVAL;
+        if (dt_next_min_dev && (overlaps(dt_next_min_dev, sizeof(double), dt_dev, ndt) ||
+                                overlaps(dt_next_min_dev, sizeof(double), dt_next_dev, nn)))
+            return HYDRO_EINVAL;
+    }
     if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
     if (ws_bytes < P->ws_bytes) return HYDRO_ENOWS;
     Launch L = batch_launch(P, (double *const *)U_ptrs_dev, U_new_ptrs_dev, ws_dev, dt_dev,
                             dt_stride);
+    L.dtn = (unsigned long long *)dt_next_dev;
+    L.dtn_min = (unsigned long long *)dt_next_min_dev;
     return enqueue_advance(L, P->grid, P->pre_dev, prm, err_dev, (hipStream_t)stream);
+}
+
+hydro_status hydro_fill_ghosts_boxes(int nb, double *const *U_ptrs_dev, const void *plan,
+                                     void *stream)
+{
+    const Plan *P = (const Plan *)plan;
+    if (!P || nb != P->nb || !U_ptrs_dev) return HYDRO_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Launch L = batch_launch(P, U_ptrs_dev, nullptr, nullptr, nullptr, 0);
+    L.pre = P->pre_dev[ST_FILL];
+    prof(PG_FILL, 0, st);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)P->grid[ST_FILL]), dim3(kBlock), 0, st, L,
+                       (unsigned long long *)nullptr, (unsigned long long *)nullptr);
+    prof(PG_FILL, 1, st);
+    return launch_status();
 }
 
 int hydro_stage_count(void) { return PG_COUNT; }

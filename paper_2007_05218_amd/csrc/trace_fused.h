@@ -44,6 +44,12 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     Box1 o = resolve(L);
     const Geo &g = o.g;
     const WS &ws = o.ws;
+    if (o.blk == 0 && threadIdx.x == 0) {
+        // the next step's timestep, which the flux kernel (launched after
+        // this one) reduces into, starts at +inf
+        if (o.dtn) *o.dtn = kInfBits;
+        if (L.dtn_min && o.b == 0) *L.dtn_min = kInfBits;
+    }
     const int BX = g.tbx1, BY = kTT / g.tbx1;
     const int RW = BX + 4, RH = BY + 4;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], ng = g.ng;

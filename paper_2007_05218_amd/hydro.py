@@ -24,7 +24,7 @@ ERR_NONFINITE, ERR_RHO, ERR_P, ERR_FALLBACK = 1, 2, 4, 8
 EXPORTS = ("hydro_state_elems", "hydro_workspace_bytes", "hydro_fill_ghosts", "estimate_dt",
            "advance_box", "estimate_dt_boxes", "advance_boxes", "hydro_plan_create",
            "hydro_plan_destroy", "hydro_status_string", "hydro_stage_count",
-           "hydro_stage_name", "hydro_set_stage_events")
+           "hydro_stage_name", "hydro_set_stage_events", "hydro_fill_ghosts_boxes")
 
 
 class HydroBox(C.Structure):
@@ -63,10 +63,10 @@ def lib():
         L.hydro_workspace_bytes.restype = C.c_size_t
         L.hydro_fill_ghosts.argtypes = [vp, bp, vp]
         L.estimate_dt.argtypes = [vp, bp, pp, vp, vp]
-        L.advance_box.argtypes = [vp, vp, bp, pp, vp, vp, C.c_size_t, vp, vp]
+        L.advance_box.argtypes = [vp, vp, bp, pp, vp, vp, vp, C.c_size_t, vp, vp]
         L.estimate_dt_boxes.argtypes = [C.c_int, vp, vp, pp, vp, vp, vp]
-        L.advance_boxes.argtypes = [C.c_int, vp, vp, vp, pp, vp, C.c_int, vp, C.c_size_t,
-                                    vp, vp]
+        L.advance_boxes.argtypes = [C.c_int, vp, vp, vp, pp, vp, C.c_int, vp, vp, vp,
+                                    C.c_size_t, vp, vp]
         L.hydro_plan_create.argtypes = [bp, C.c_int, C.c_char_p, C.POINTER(vp)]
         L.hydro_plan_destroy.argtypes = [vp]
         L.hydro_plan_destroy.restype = None
@@ -78,8 +78,9 @@ def lib():
         L.hydro_set_stage_events.restype = C.c_int
         L.hydro_status_string.argtypes = [C.c_int]
         L.hydro_status_string.restype = C.c_char_p
+        L.hydro_fill_ghosts_boxes.argtypes = [C.c_int, vp, vp, vp]
         for f in ("hydro_fill_ghosts", "estimate_dt", "advance_box", "estimate_dt_boxes",
-                  "advance_boxes", "hydro_plan_create"):
+                  "advance_boxes", "hydro_plan_create", "hydro_fill_ghosts_boxes"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -142,12 +143,14 @@ def estimate_dt(U, box, prm, dt, stream=None):
                                             _stream(stream)))
 
 
-def advance_box(U, Unew, box, prm, dt, ws, err, stream=None):
-    """One step of length dt[0] from U (ghosts filled) into the valid cells of Unew."""
+def advance_box(U, Unew, box, prm, dt, ws, err, stream=None, dt_next=None):
+    """One step of length dt[0] from U (ghosts filled) into the valid cells of
+    Unew; with ``dt_next`` (1-element device tensor) also Unew's CFL timestep."""
     _check_state(U, box)
     _check_state(Unew, box)
     _check("advance_box", lib().advance_box(_ptr(U), _ptr(Unew), C.byref(make_box(box)),
                                             C.byref(make_params(prm)), _ptr(dt),
+                                            _ptr(dt_next) if dt_next is not None else None,
                                             _ptr(ws, torch.uint8), ws.numel(),
                                             _ptr(err, torch.int32), _stream(stream)))
 
@@ -168,13 +171,30 @@ class Box:
         self.Unew = torch.empty_like(self.U)
         self.ws = alloc_workspace(self.box, device)
         self.dt = torch.zeros(1, dtype=torch.float64, device=device)
+        self.dt_next = torch.zeros(1, dtype=torch.float64, device=device)
         self.err = torch.zeros(1, dtype=torch.int32, device=device)
         self.t = torch.zeros(1, dtype=torch.float64, device=device)
+        self.have_dt = False  # dt_next holds the current state's timestep
 
     def step(self, stream=None):
-        estimate_dt(self.U, self.box, self.prm, self.dt, stream)
-        advance_box(self.U, self.Unew, self.box, self.prm, self.dt, self.ws, self.err, stream)
+        """Ghost fill + CFL timestep + advance.  The timestep of a state the
+        previous step produced comes from that step's advance (bitwise the
+        estimate_dt value), so only the ghost fill runs before the advance;
+        ``self.dt`` is the timestep of the step just taken."""
+        if self.have_dt:
+            fill_ghosts(self.U, self.box, stream)
+            self.dt, self.dt_next = self.dt_next, self.dt
+        else:
+            estimate_dt(self.U, self.box, self.prm, self.dt, stream)
+        advance_box(self.U, self.Unew, self.box, self.prm, self.dt, self.ws, self.err, stream,
+                    dt_next=self.dt_next)
         self.U, self.Unew = self.Unew, self.U
+        self.have_dt = True
+
+    def invalidate_dt(self):
+        """Call after changing ``self.U`` directly: the next step computes its
+        timestep from the state instead of taking the carried one."""
+        self.have_dt = False
 
     def run(self, steps, stream=None):
         for _ in range(steps):
@@ -223,12 +243,23 @@ def estimate_dt_boxes(plan, U_ptrs, prm, dt, dt_min=None, stream=None):
         _ptr(dt_min) if dt_min is not None else None, _stream(stream)))
 
 
-def advance_boxes(plan, U_ptrs, Unew_ptrs, prm, dt, ws, err, dt_stride=1, stream=None):
-    """Advance every box of the plan by dt[b] (dt_stride=1) or dt[0] (dt_stride=0)."""
+def advance_boxes(plan, U_ptrs, Unew_ptrs, prm, dt, ws, err, dt_stride=1, stream=None,
+                  dt_next=None, dt_next_min=None):
+    """Advance every box of the plan by dt[b] (dt_stride=1) or dt[0]
+    (dt_stride=0); with ``dt_next`` also every new state's CFL timestep, and
+    with ``dt_next_min`` their minimum."""
     _check("advance_boxes", lib().advance_boxes(
         plan.nb, _ptr(U_ptrs, torch.int64), _ptr(Unew_ptrs, torch.int64), plan.handle,
-        C.byref(make_params(prm)), _ptr(dt), dt_stride, _ptr(ws, torch.uint8), ws.numel(),
-        _ptr(err, torch.int32), _stream(stream)))
+        C.byref(make_params(prm)), _ptr(dt), dt_stride,
+        _ptr(dt_next) if dt_next is not None else None,
+        _ptr(dt_next_min) if dt_next_min is not None else None,
+        _ptr(ws, torch.uint8), ws.numel(), _ptr(err, torch.int32), _stream(stream)))
+
+
+def fill_ghosts_boxes(plan, U_ptrs, stream=None):
+    """Ghost fill of every box of the plan (one launch)."""
+    _check("hydro_fill_ghosts_boxes", lib().hydro_fill_ghosts_boxes(
+        plan.nb, _ptr(U_ptrs, torch.int64), plan.handle, _stream(stream)))
 
 
 class Level:
@@ -246,19 +277,36 @@ class Level:
         self.ws = torch.empty(max(self.plan.ws_bytes, 256), dtype=torch.uint8, device=device)
         self.dt = torch.zeros(len(states), dtype=torch.float64, device=device)
         self.dt_min = torch.zeros(1, dtype=torch.float64, device=device)
+        self.dt_next = torch.zeros(len(states), dtype=torch.float64, device=device)
+        self.dt_next_min = torch.zeros(1, dtype=torch.float64, device=device)
         self.err = torch.zeros(1, dtype=torch.int32, device=device)
         self.shared_dt = shared_dt
+        self.have_dt = False  # dt_next / dt_next_min hold the current states' timesteps
 
     def step(self, stream=None):
-        estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, self.dt_min, stream)
+        """Ghost fill + timesteps + advance of every box (the timesteps of
+        states the previous step produced come from that step's advance)."""
+        if self.have_dt:
+            fill_ghosts_boxes(self.plan, self.pa, stream)
+            self.dt, self.dt_next = self.dt_next, self.dt
+            self.dt_min, self.dt_next_min = self.dt_next_min, self.dt_min
+        else:
+            estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, self.dt_min, stream)
         if self.shared_dt:
             advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt_min, self.ws, self.err,
-                          dt_stride=0, stream=stream)
+                          dt_stride=0, stream=stream, dt_next=self.dt_next,
+                          dt_next_min=self.dt_next_min)
         else:
             advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt, self.ws, self.err,
-                          dt_stride=1, stream=stream)
+                          dt_stride=1, stream=stream, dt_next=self.dt_next)
         self.U, self.Unew = self.Unew, self.U
         self.pa, self.pb = self.pb, self.pa
+        self.have_dt = True
+
+    def invalidate_dt(self):
+        """Call after changing the states directly: the next step computes the
+        timesteps from them instead of taking the carried ones."""
+        self.have_dt = False
 
     def run(self, steps, stream=None):
         for _ in range(steps):

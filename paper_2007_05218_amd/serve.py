@@ -97,6 +97,8 @@ class GpuExecutor:
         self.plan = self.hydro.Plan(boxes)
         self.ws = torch.empty(max(self.plan.ws_bytes, 256), dtype=torch.uint8, device=self.device)
         self.dt = torch.zeros(len(reqs), dtype=torch.float64, device=self.device)
+        self.dt_next = torch.zeros(len(reqs), dtype=torch.float64, device=self.device)
+        self.have_dt = False  # the active set changed: timesteps from estimate_dt_boxes
         self._pointers()
 
     def _pointers(self):
@@ -106,9 +108,14 @@ class GpuExecutor:
     # -- one iteration: every active request advances one step with its own dt
     def step(self):
         h = self.hydro
-        h.estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, None)
+        if self.have_dt:  # timesteps of the states the previous iteration produced
+            h.fill_ghosts_boxes(self.plan, self.pa)
+            self.dt, self.dt_next = self.dt_next, self.dt
+        else:
+            h.estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, None)
         h.advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt, self.ws, self.err,
-                        dt_stride=1)
+                        dt_stride=1, dt_next=self.dt_next)
+        self.have_dt = True
         for r in self.active:
             r.handle["U"], r.handle["Un"] = r.handle["Un"], r.handle["U"]
         self.pa, self.pb = self.pb, self.pa

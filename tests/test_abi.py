@@ -65,7 +65,7 @@ def test_invalid_boxes_rejected(bad):
     fake = C.c_void_p(256)
     assert L.estimate_dt(fake, C.byref(b), C.byref(p), fake, None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts(fake, C.byref(b), None) == hydro.HYDRO_EINVAL
-    assert L.advance_box(fake, C.c_void_p(1 << 40), C.byref(b), C.byref(p), fake, fake,
+    assert L.advance_box(fake, C.c_void_p(1 << 40), C.byref(b), C.byref(p), fake, None, fake,
                          1 << 40, fake, None) == hydro.HYDRO_EINVAL
     arr = (hydro.HydroBox * 1)(b)
     h = C.c_void_p()
@@ -93,17 +93,21 @@ def test_null_and_overlap_rejected():
     ws = C.c_void_p(1 << 34)
     nbytes = hydro.workspace_bytes(d)
     # U_new overlapping U
-    assert L.advance_box(a, C.c_void_p((1 << 30) + 8), C.byref(b), C.byref(p), a, ws, nbytes,
-                         a, None) == hydro.HYDRO_EINVAL
+    assert L.advance_box(a, C.c_void_p((1 << 30) + 8), C.byref(b), C.byref(p), a, None, ws,
+                         nbytes, a, None) == hydro.HYDRO_EINVAL
     # workspace misaligned
-    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), a,
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), a, None,
                          C.c_void_p((1 << 34) + 8), nbytes, a, None) == hydro.HYDRO_EINVAL
     # workspace too small
-    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), a, ws, nbytes - 256,
-                         a, None) == hydro.HYDRO_ENOWS
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), a, None, ws,
+                         nbytes - 256, a, None) == hydro.HYDRO_ENOWS
+    # next-step timestep overlapping the one in use
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), C.c_void_p(1 << 36),
+                         C.c_void_p((1 << 36) + 4), ws, nbytes, a, None) == hydro.HYDRO_EINVAL
     assert L.estimate_dt(None, C.byref(b), C.byref(p), a, None) == hydro.HYDRO_EINVAL
-    assert L.advance_boxes(1, a, a, None, C.byref(p), a, 1, ws, nbytes, a,
+    assert L.advance_boxes(1, a, a, None, C.byref(p), a, 1, None, None, ws, nbytes, a,
                            None) == hydro.HYDRO_EINVAL
+    assert L.hydro_fill_ghosts_boxes(1, a, None, None) == hydro.HYDRO_EINVAL
 
 
 def test_status_strings():

@@ -125,3 +125,35 @@ def test_autotuner_runs(gpu):
     gpu.Plan(boxes, autotune.table_json(table)).close()
     # a table keeping one kernel's built-in tile is accepted
     gpu.Plan(boxes, autotune.table_json({"16x32x16": (16, 8) + autotune.BUILTIN})).close()
+    # the level-wide check keeps the table only if the level runs faster with it
+    states = [inputs.smooth(b["n"], seed=i)[0] for i, b in enumerate(boxes)]
+    kept, ms_builtin, ms_table = autotune.validate(
+        states, boxes, inputs.params_desc(), {"16x32x16": (8, 4, 8, 4)}, steps=1, rounds=1)
+    assert ms_builtin > 0 and ms_table > 0
+    assert kept == ({"16x32x16": (8, 4, 8, 4)} if ms_table < ms_builtin else {})
+
+
+def test_batched_fused_next_timesteps(gpu):
+    # advance_boxes' dt_next / dt_next_min equal estimate_dt_boxes of the new
+    # states, bit for bit, with per-box and with shared timesteps
+    import torch
+    states, boxes, prm = inputs.level(nboxes=12, seed=5)
+    plan = gpu.Plan(boxes)
+    U = [torch.as_tensor(u).cuda() for u in states]
+    Un = [torch.empty_like(u) for u in U]
+    pa, pb = gpu.pointer_array(U), gpu.pointer_array(Un)
+    ws = torch.empty(max(plan.ws_bytes, 256), dtype=torch.uint8, device="cuda")
+    nb = len(boxes)
+    dt, dtn, dte = (torch.zeros(nb, dtype=torch.float64, device="cuda") for _ in range(3))
+    dmin, dnmin, demin = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(3))
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for shared in (True, False):
+        gpu.estimate_dt_boxes(plan, pa, prm, dt, dmin)
+        gpu.advance_boxes(plan, pa, pb, prm, dmin if shared else dt, ws, err,
+                          dt_stride=0 if shared else 1, dt_next=dtn, dt_next_min=dnmin)
+        gpu.estimate_dt_boxes(plan, pb, prm, dte, demin)
+        torch.cuda.synchronize()
+        assert torch.equal(dtn, dte) and dnmin.item() == demin.item()
+        assert dnmin.item() == dte.min().item()
+        pa, pb = pb, pa
+    plan.close()

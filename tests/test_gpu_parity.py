@@ -166,3 +166,25 @@ def test_full_size_first_step_sampled(gpu, orc, case):
         err, bw = compare(g[sl], Unew[sl])
         print("region", lo, hi, err, bw, flush=True)
         assert err <= TOL and bw == 1.0
+
+
+@pytest.mark.parametrize("case", ["sod32", "rt40", "ragged"])
+def test_fused_next_timestep_equals_estimate_dt(gpu, case):
+    # advance_box's dt_next is the CFL timestep of the new state, bit for bit
+    # what estimate_dt gives for it
+    import torch
+    U, box, prm = {"sod32": lambda: inputs.sod(32), "rt40": lambda: inputs.rt(40, seed=4),
+                   "ragged": lambda: inputs.smooth((37, 29, 23), seed=7)}[case]()
+    Ud = torch.as_tensor(U).cuda()
+    Un = torch.empty_like(Ud)
+    ws = gpu.alloc_workspace(box)
+    dt, dtn, dte = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(3))
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        gpu.estimate_dt(Ud, box, prm, dt)
+        gpu.advance_box(Ud, Un, box, prm, dt, ws, err, dt_next=dtn)
+        gpu.estimate_dt(Un, box, prm, dte)
+        torch.cuda.synchronize()
+        print(case, dtn.item(), dte.item(), flush=True)
+        assert dtn.item() == dte.item() and dtn.item() > 0.0
+        Ud, Un = Un, Ud
