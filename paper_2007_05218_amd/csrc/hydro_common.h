@@ -85,13 +85,27 @@ struct Parab {
     double aL, aR, dA, a6;
 };
 
+// unlimited interface value between cells with averages al, ar and slopes
+// sl, sr (the fourth-order interpolant with the limited slopes)
+__device__ __forceinline__ double ppm_iface(double al, double ar, double sl, double sr)
+{
+    return 0.5 * (al + ar) - (sr - sl) * kC6;
+}
+
+// the parabola limiter applied to cell average a2 with unlimited interface
+// values aL (low face) and aR (high face)
+__device__ __forceinline__ Parab ppm_limit(double a2, double aL, double aR);
+
 __device__ __forceinline__ Parab ppm(double a0, double a1, double a2, double a3, double a4)
 {
     double sm = mc_slope(a0, a1, a2);
     double s0 = mc_slope(a1, a2, a3);
     double sp = mc_slope(a2, a3, a4);
-    double aL = 0.5 * (a1 + a2) - (s0 - sm) * kC6;
-    double aR = 0.5 * (a2 + a3) - (sp - s0) * kC6;
+    return ppm_limit(a2, ppm_iface(a1, a2, sm, s0), ppm_iface(a2, a3, s0, sp));
+}
+
+__device__ __forceinline__ Parab ppm_limit(double a2, double aL, double aR)
+{
     if ((aR - a2) * (a2 - aL) <= 0.0) {
         aL = a2;
         aR = a2;
@@ -158,19 +172,13 @@ __device__ __forceinline__ void set_lab(Face &f, int d, double r, double un, dou
     }
 }
 
-__device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (&uns)[5],
-                                           const double (&t1s)[5], const double (&t2s)[5],
-                                           const double (&ps)[5], double c, double ri, int d,
-                                           double dtdx, Face &hi, Face &lo)
+// the tracing proper, from the five limited parabolae of the cell
+__device__ __forceinline__ void trace_parab(const Parab &Pr, const Parab &Pu, const Parab &P1,
+                                            const Parab &P2, const Parab &Pp, double rho,
+                                            double un, double c, double ri, int d, double dtdx,
+                                            Face &hi, Face &lo)
 {
-    const double rho = rs[2];
-    const double un = uns[2];
     const double lm = un - c, l0 = un, lp = un + c;
-    Parab Pr = ppm(rs[0], rs[1], rs[2], rs[3], rs[4]);
-    Parab Pu = ppm(uns[0], uns[1], uns[2], uns[3], uns[4]);
-    Parab P1 = ppm(t1s[0], t1s[1], t1s[2], t1s[3], t1s[4]);
-    Parab P2 = ppm(t2s[0], t2s[1], t2s[2], t2s[3], t2s[4]);
-    Parab Pp = ppm(ps[0], ps[1], ps[2], ps[3], ps[4]);
     const double rc = rho * c;
     const double cs2 = c * c;
     const double ics2 = 1.0 / cs2;
@@ -205,6 +213,48 @@ __device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (
         set_lab(lo, d, r_r - (az + ap), r_u - cor * ap, t1, t2, r_p - cs2 * ap);
     }
 }
+
+__device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (&uns)[5],
+                                           const double (&t1s)[5], const double (&t2s)[5],
+                                           const double (&ps)[5], double c, double ri, int d,
+                                           double dtdx, Face &hi, Face &lo)
+{
+    trace_parab(ppm(rs[0], rs[1], rs[2], rs[3], rs[4]),
+                ppm(uns[0], uns[1], uns[2], uns[3], uns[4]),
+                ppm(t1s[0], t1s[1], t1s[2], t1s[3], t1s[4]),
+                ppm(t2s[0], t2s[1], t2s[2], t2s[3], t2s[4]),
+                ppm(ps[0], ps[1], ps[2], ps[3], ps[4]), rs[2], uns[2], c, ri, d, dtdx, hi, lo);
+}
+
+// PPM along a column marched cell by cell (the z-direction of the marching
+// kernels): the slope and the high interface value a cell computes are its
+// upper neighbour's low slope and low interface value, so each step forms
+// one new slope and one interface value.  State at cell k: a = a(k),
+// an = a(k+1), s = slope(k), iL = unlimited interface value at k-1/2.
+struct PPMColumn {
+    double a, an, s, iL;
+    // start at cell k from a(k-2) .. a(k+1)
+    __device__ __forceinline__ void init(double am2, double am1, double a0, double ap1)
+    {
+        const double sm = mc_slope(am2, am1, a0);
+        a = a0;
+        an = ap1;
+        s = mc_slope(am1, a0, ap1);
+        iL = ppm_iface(am1, a0, sm, s);
+    }
+    // the limited parabola of the current cell, given a(k+2); then move to k+1
+    __device__ __forceinline__ Parab step(double ap2)
+    {
+        const double sp = mc_slope(a, an, ap2);
+        const double iR = ppm_iface(a, an, s, sp);
+        const Parab P = ppm_limit(a, iL, iR);
+        a = an;
+        an = ap2;
+        s = sp;
+        iL = iR;
+        return P;
+    }
+};
 
 // ---------------------------------------------------------------- HLLC
 

@@ -6,14 +6,14 @@
 // Output (HBM workspace): the traced face states of every cell one beyond
 // the valid region -- the input of the fused flux kernel, which also solves
 // the round-1 Riemann problems from them (a round-1 flux costs less to
-// recompute there than its five doubles cost to store here and read back
-// there).  Each cell's primitives are
-// computed once per block: a plane of the tile plus a two-cell ring enters
-// an LDS ring of three planes (the x/y stencils read the centre plane from
-// it) and each column copies its own values into a five-plane register
-// window for the z stencil.  This is the one-zone-per-thread stencil of the
-// paper's Sec. III with the neighbouring slopes staged on chip instead of
-// recomputed from global memory.
+// compute there than its five doubles cost to store here and read back
+// there).  Each cell's primitives are computed once per block: a plane of
+// the tile plus a two-cell ring enters an LDS ring of three planes (the x/y
+// stencils read the centre plane from it) and each column marches its own
+// z-direction PPM, one new slope and interface value per plane.  This is the
+// one-zone-per-thread stencil of the paper's Sec. III with the neighbouring
+// primitives staged on chip instead of re-read and re-converted from global
+// memory.
 //
 // Tile: a 256-thread block covers BX x BY output columns
 // [x0, x0+BX) x [y0, y0+BY) of the traced region and marches over its
@@ -118,51 +118,50 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         }
     };
 
-    // z-window of the own column: planes p-2 .. p+2 (index 0 .. 4)
-    double wr[5], wu[5], wv[5], ww[5], wp[5];
-    for (int z = z0 - 2; z <= z0 + 1; ++z) {
-        fetch(z);
-        commit(z);
-        __syncthreads();
-        const int slot = (z + 6) % 3;
-        const int k = z - (z0 - 2) + 1;  // window index of plane z before the first shift
-        wr[k] = pl[slot][0][rc];
-        wu[k] = pl[slot][1][rc];
-        wv[k] = pl[slot][2][rc];
-        ww[k] = pl[slot][3][rc];
-        wp[k] = pl[slot][4][rc];
-        __syncthreads();
+    // z-direction PPM of the own column (rho, u, v, w, p), marched with the
+    // planes; started from planes z0-2 .. z0+1
+    PPMColumn zr, zu, zv, zw, zp;
+    {
+        double c0[4][5];
+        for (int z = z0 - 2; z <= z0 + 1; ++z) {
+            fetch(z);
+            commit(z);
+            __syncthreads();
+            const int slot = (z + 6) % 3;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) c0[z - (z0 - 2)][v] = pl[slot][v][rc];
+            __syncthreads();
+        }
+        zr.init(c0[0][0], c0[1][0], c0[2][0], c0[3][0]);
+        zu.init(c0[0][1], c0[1][1], c0[2][1], c0[3][1]);
+        zv.init(c0[0][2], c0[1][2], c0[2][2], c0[3][2]);
+        zw.init(c0[0][3], c0[1][3], c0[2][3], c0[3][3]);
+        zp.init(c0[0][4], c0[1][4], c0[2][4], c0[3][4]);
     }
-    wr[0] = wu[0] = wv[0] = ww[0] = wp[0] = 0.0;
     fetch(z0 + 2);
 
     for (int p = z0; p < z1; ++p) {
         commit(p + 2);
         if (p + 1 < z1) fetch(p + 3);
         __syncthreads();
-        {  // shift the window and append plane p+2
+        // the cell's own primitives, and its z-parabolae given plane p+2
+        const double rho = zr.a, wz = zw.a;
+        const double ri = 1.0 / rho;  // as the cell's primitive conversion forms it
+        const double c = sound_ri(gamma, zp.a, ri);
+        Parab Pr, Pu, Pv, Pw, Pp;
+        {
             const int slot = (p + 2 + 6) % 3;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                wr[k] = wr[k + 1];
-                wu[k] = wu[k + 1];
-                wv[k] = wv[k + 1];
-                ww[k] = ww[k + 1];
-                wp[k] = wp[k + 1];
-            }
-            wr[4] = pl[slot][0][rc];
-            wu[4] = pl[slot][1][rc];
-            wv[4] = pl[slot][2][rc];
-            ww[4] = pl[slot][3][rc];
-            wp[4] = pl[slot][4][rc];
+            Pr = zr.step(pl[slot][0][rc]);
+            Pu = zu.step(pl[slot][1][rc]);
+            Pv = zv.step(pl[slot][2][rc]);
+            Pw = zw.step(pl[slot][3][rc]);
+            Pp = zp.step(pl[slot][4][rc]);
         }
-        const double ri = 1.0 / wr[2];  // as the cell's primitive conversion forms it
-        const double c = sound_ri(gamma, wp[2], ri);
         const int slot = (p + 6) % 3;
         Face hi, lo;
         const char *pp = ws.plane(p);
         // ------------------------------------------------ z trace
-        trace_cell(wr, ww, wu, wv, wp, c, ri, 2, dtdz, hi, lo);
+        trace_parab(Pr, Pw, Pu, Pv, Pp, rho, wz, c, ri, 2, dtdz, hi, lo);
         if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
         if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
         if (gz != 0.0) { hi.w = hi.w + h * gz; lo.w = lo.w + h * gz; }
