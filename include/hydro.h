@@ -106,7 +106,9 @@ hydro_status hydro_fill_ghosts(double *U_dev, const hydro_box *box, void *stream
  *     dt = cfl * min over axes d of dx_d / max over valid cells (|u_d| + c),
  * c = sqrt(gamma p / rho).  The result is exact (min/max are exact) and
  * independent of the launch.  *dt_dev is used as the reduction's accumulator;
- * no other scratch is needed. */
+ * no other scratch is needed.  For a state with rho <= 0 or p <= 0 or
+ * non-finite values somewhere (what advance_box flags with error bits 1, 2,
+ * 4) the value is unspecified. */
 hydro_status estimate_dt(double *U_dev, const hydro_box *box, const hydro_params *prm,
                          double *dt_dev, void *stream);
 
@@ -121,8 +123,8 @@ hydro_status estimate_dt(double *U_dev, const hydro_box *box, const hydro_params
  * bitwise what estimate_dt gives for U_new_dev (its valid cells decide it),
  * reduced in the update's epilogue instead of a separate pass over U_new:
  * a stepping loop then needs only hydro_fill_ghosts before the next
- * advance_box.  It must not overlap *dt_dev (HYDRO_EINVAL).  With a
- * non-finite new state the value is unspecified (error bit 1 is raised). */
+ * advance_box.  It must not overlap *dt_dev (HYDRO_EINVAL).  When the
+ * new state raises error bit 1, 2 or 4 the value is unspecified. */
 hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box *box,
                          const hydro_params *prm, const double *dt_dev, double *dt_next_dev,
                          void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream);
