@@ -4,9 +4,10 @@
 //
 // Input (HBM workspace, written by the trace kernel): the traced face states
 // of every cell in all three directions; the round-1 fluxes are solved here
-// from them.  Output: the new state of the tile's cells.  Nothing else goes
-// back to HBM: in-plane neighbour exchanges go through LDS, and the
-// z-direction couplings (fluxes through z-faces and the z-differences of
+// from them.  Output: the new state of the tile's cells (and, optionally,
+// the CFL timestep of the new state).  Nothing else goes back to HBM:
+// x-neighbour exchanges stay inside the wavefront (DPP lane shifts),
+// y-neighbour exchanges go through LDS, and the z-direction couplings (fluxes through z-faces and the z-differences of
 // the (z|s) fluxes) are carried from plane to plane in registers or, for
 // values a lane alone needs a plane later, in its own LDS slots (which keeps
 // the kernel within its register budget: spilled registers would go to
@@ -180,12 +181,50 @@ __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long n
     return T;
 }
 
-__host__ inline long long fused_blocks(const Geo &g)
+// x-neighbour exchange inside the wavefront: tile rows are runs of BX lanes
+// (BX divides 64), so a lane's low and high x-neighbours are lanes t-1 and
+// t+1 of its own wavefront, and a DPP shift of the whole wavefront by one
+// lane delivers their values with no LDS traffic and no barrier.  (A lane at
+// a row end receives another row's value or its own; nothing it computes
+// from it is used.)
+__device__ __forceinline__ double dpp_prev(double v)  // lane t-1's v
 {
-    const int TX = g.tbx2 - 2, TY = kFT / g.tbx2 - 2;
-    long long ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
-    long long nzs = (g.n[2] + g.tzs2 - 1) / g.tzs2;
-    return ntx * nty * nzs;
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x138, 0xF, 0xF,
+                                               false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double dpp_next(double v)  // lane t+1's v
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x130, 0xF, 0xF,
+                                               false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// the low x-neighbour's state, with 1/rho formed as its writer formed it
+__device__ __forceinline__ Face prevF(const Face &f)
+{
+    Face g;
+    g.r = dpp_prev(f.r);
+    g.u = dpp_prev(f.u);
+    g.v = dpp_prev(f.v);
+    g.w = dpp_prev(f.w);
+    g.p = dpp_prev(f.p);
+    g.ri = 1.0 / g.r;
+    return g;
+}
+// the high x-neighbour's flux minus this lane's
+__device__ __forceinline__ Flux next_minus(const Flux &f)
+{
+    Flux d;
+    d.m = dpp_next(f.m) - f.m;
+    d.mu = dpp_next(f.mu) - f.mu;
+    d.mv = dpp_next(f.mv) - f.mv;
+    d.mw = dpp_next(f.mw) - f.mw;
+    d.e = dpp_next(f.e) - f.e;
+    return d;
 }
 
 #ifndef HYDRO_FUSED_WAVES
@@ -194,9 +233,12 @@ __host__ inline long long fused_blocks(const Geo &g)
 __global__ void __launch_bounds__(kFT) __attribute__((amdgpu_waves_per_eu(HYDRO_FUSED_WAVES)))
 k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz, int *err_dev)
 {
-    __shared__ XBuf xa, xb;
-    // own-lane carries: dF2xz, dF2yz, F3z of the previous plane, F1z through
-    // the current plane's low face
+    // y-neighbour exchanges alternate between two buffers, so each needs one
+    // barrier (its readers of two exchanges back are past the barrier of the
+    // exchange between); x-neighbour exchanges stay in the wavefront (DPP)
+    __shared__ XBuf ya, yb;
+    // own-lane carries: dF2xz, dF2yz of the previous plane, F3z through its
+    // low face, F1z through the current plane's low face
     __shared__ double cz[20][kFT];
     Box1 o = resolve(L);
     const Geo &g = o.g;
@@ -209,7 +251,6 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
     // loads come from the clamped column (inside the traced region); results
     // of columns outside it are never used
     const int xc = min(x, n0), yc = min(y, n1);
-    const int tL = tx >= 1 ? t - 1 : t, tR = tx + 1 < T.BX ? t + 1 : t;
     const int tD = ty >= 1 ? t - T.BX : t, tU = ty + 1 < T.BY ? t + T.BX : t;
     // neighbour lanes present in the tile: a value that depends on an
     // exchange with a missing neighbour is never used and raises no error bit
@@ -253,66 +294,60 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         const Face qz_lo = load_face_b(pq, wo, QLO(2, 0)), qz_hi = load_face_b(pq, wo, QHI(2, 0));
         // ---------------------------------------------------- round-1 fluxes
         // through each lane's low x/y faces (the low neighbour's high state
-        // comes through LDS) and through the plane's high z-face; the x/y
-        // differences take the high neighbour's flux through LDS, the z
-        // difference the flux carried from the plane below
-        putF(xa.v, 0, t, qx_hi);
-        putF(xa.v, 5, t, qy_hi);
+        // from the neighbour lane: x in the wavefront, y through LDS) and
+        // through the plane's high z-face; their differences over the cell
+        putF(ya.v, 0, t, qy_hi);
         const Flux F1zn = hllc(with_ri(qz_hi),
                                with_ri(load_face_b(ws.plane(q + 1), wo, QLO(2, 0))),  // next plane
                                2, gamma, igm1);
+        const Flux dF1x = next_minus(hllc(prevF(qx_hi), with_ri(qx_lo), 0, gamma, igm1));
         __syncthreads();
-        {
-            const Flux F1x = hllc(getF(xa.v, 0, tL), with_ri(qx_lo), 0, gamma, igm1);
-            const Flux F1y = hllc(getF(xa.v, 5, tD), with_ri(qy_lo), 1, gamma, igm1);
-            putX(xb.v, 0, t, F1x);
-            putX(xb.v, 5, t, F1y);
-        }
-        __syncthreads();
-        const Flux dF1x = fdiff(getX(xb.v, 0, tR), getX(xb.v, 0, t));
-        const Flux dF1y = fdiff(getX(xb.v, 5, tU), getX(xb.v, 5, t));
+        putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), with_ri(qy_lo), 1, gamma, igm1));
         // (the round-1 z-flux carried from the plane below is never used
         // before the first plane's)
         const Flux dF1z = fdiff(F1zn, getX(cz, 15, t));
         putX(cz, 15, t, F1zn);
         __syncthreads();
+        const Flux dF1y = fdiff(getX(yb.v, 0, tU), getX(yb.v, 0, t));
 
-        // ---------------------------------------------------- A: high corner states
+        // ---------------------------------------------------- corner states, round-2 fluxes
         int fb;
+        {  // high (y|x), (y|z) states to the upper neighbour
+            Face h = corner_state(qy_hi, dF1x, fx3, gm1, igm1, fb);  // (y|x)
+            if (fb && hL && hR && ry_fh && rx_c && rz_w) err |= fb;
+            putF(ya.v, 0, t, h);
+            h = corner_state(qy_hi, dF1z, fz3, gm1, igm1, fb);  // (y|z)
+            if (fb && ry_fh && rz_c && rx_w) err |= fb;
+            putF(ya.v, 5, t, h);
+        }
+        // x-families: the low neighbour's high state from the neighbour lane;
+        // the x-differences of the fluxes right away
+        Flux dxy, dxz;
         {
             Face h = corner_state(qx_hi, dF1y, fy3, gm1, igm1, fb);  // (x|y)
             if (fb && hD && hU && rx_fh && ry_c && rz_w) err |= fb;
-            putF(xa.v, 0, t, h);
-            h = corner_state(qy_hi, dF1x, fx3, gm1, igm1, fb);  // (y|x)
-            if (fb && hL && hR && ry_fh && rx_c && rz_w) err |= fb;
-            putF(xa.v, 5, t, h);
-            h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
-            if (fb && rx_fh && rz_c && ry_w) err |= fb;
-            putF(xb.v, 0, t, h);
-            h = corner_state(qy_hi, dF1z, fz3, gm1, igm1, fb);  // (y|z)
-            if (fb && ry_fh && rz_c && rx_w) err |= fb;
-            putF(xb.v, 5, t, h);
-        }
-        __syncthreads();
-        // ---------------------------------------------------- B: round-2 fluxes
-        Flux F2xy, F2yx, F2xz, F2yz;
-        {
             Face l = corner_state(qx_lo, dF1y, fy3, gm1, igm1, fb);
             if (fb && hD && hU && rx_f && ry_c && rz_w) err |= fb;
-            F2xy = hllc(getF(xa.v, 0, tL), l, 0, gamma, igm1);
-            l = corner_state(qy_lo, dF1x, fx3, gm1, igm1, fb);
-            if (fb && hL && hR && ry_f && rx_c && rz_w) err |= fb;
-            F2yx = hllc(getF(xa.v, 5, tD), l, 1, gamma, igm1);
+            dxy = next_minus(hllc(prevF(h), l, 0, gamma, igm1));
+            h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
+            if (fb && rx_fh && rz_c && ry_w) err |= fb;
             l = corner_state(qx_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && rx_f && rz_c && ry_w) err |= fb;
-            F2xz = hllc(getF(xb.v, 0, tL), l, 0, gamma, igm1);
-            l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);
+            dxz = next_minus(hllc(prevF(h), l, 0, gamma, igm1));
+        }
+        __syncthreads();
+        {  // y-families
+            Face l = corner_state(qy_lo, dF1x, fx3, gm1, igm1, fb);  // (y|x)
+            if (fb && hL && hR && ry_f && rx_c && rz_w) err |= fb;
+            putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), l, 1, gamma, igm1));
+            l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);  // (y|z)
             if (fb && ry_f && rz_c && rx_w) err |= fb;
-            F2yz = hllc(getF(xb.v, 5, tD), l, 1, gamma, igm1);
+            putX(yb.v, 5, t, hllc(getF(ya.v, 5, tD), l, 1, gamma, igm1));
         }
         // z-families: the flux through the z-face between q-1 and q
+        const bool rz_f = inr(q, 0, n2), rz_fh = inr(q + 1, 0, n2);
+        Flux dzx, dzy;
         {
-            const bool rz_f = inr(q, 0, n2), rz_fh = inr(q + 1, 0, n2);
             Face l = corner_state(qz_lo, dF1x, fx3, gm1, igm1, fb);  // (z|x)
             if (fb && hL && hR && rz_f && rx_c && ry_w) err |= fb;
             Flux Fzx = hllc(c_zx_hi, l, 2, gamma, igm1);
@@ -326,122 +361,119 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             if (fb && hD && hU && rz_fh && ry_c && rx_w) err |= fb;
             c_zy_hi = h;
             // z-differences of the (z|s) fluxes of plane q-1
-            const Flux dzx = fdiff(Fzx, F2zx), dzy = fdiff(Fzy, F2zy);
+            dzx = fdiff(Fzx, F2zx);
+            dzy = fdiff(Fzy, F2zy);
             F2zx = Fzx;
             F2zy = Fzy;
-            __syncthreads();
-            // ------------------------------------------------ C: publish round-2 fluxes
-            putX(xa.v, 0, t, F2xy);
-            putX(xa.v, 5, t, F2yx);
-            putX(xb.v, 0, t, F2xz);
-            putX(xb.v, 5, t, F2yz);
-            __syncthreads();
-            // ------------------------------------------------ D: final states
-            // final z state of plane q
-            const Flux dxy = fdiff(getX(xa.v, 0, tR), getX(xa.v, 0, t));
-            const Flux dyx = fdiff(getX(xa.v, 5, tU), getX(xa.v, 5, t));
-            const bool zin = hL && hR && hD && hU && rx_c && ry_c;
-            Face zl = final_state2(qz_lo, dxy, dyx, fx2, fy2, gm1, igm1, fb);
-            if (fb && zin && rz_f) err |= fb;
-            Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, igm1, fb);
-            if (fb && zin && rz_fh) err |= fb;
-            Flux F3zq = hllc(fz_hi, zl, 2, gamma, igm1);
-            fz_hi = zh;
-            // differences of the in-plane (s|z) fluxes of plane q (used next plane)
-            const Flux dxz = fdiff(getX(xb.v, 0, tR), getX(xb.v, 0, t));
-            const Flux dyz = fdiff(getX(xb.v, 5, tU), getX(xb.v, 5, t));
-            // final x and y states of plane q-1
-            const int p = q - 1;
-            const bool pv = p >= T.z0;  // plane p is finished in this segment
-            const bool rp_c = inr(p, 0, n2 - 1);
-            const char *pp = ws.plane(p);
-            Face xl, xh, yl, yh;
-            // (lanes whose final x or y states are never used skip reading
-            // their traced states: the ring rows for x, the ring columns for y,
-            // and every lane in a segment's warm-up plane)
-            {
-                Face a = {}, b = {};
-                if (pv && hD && hU) {
-                    a = load_face_b(pp, wo, QLO(0, 0));
-                    b = load_face_b(pp, wo, QHI(0, 0));
-                }
-                const Flux dF2yz = getX(cz, 5, t);
-                xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
-                if (fb && pv && hD && hU && rx_f && ry_c && rp_c) err |= fb;
-                xh = final_state2(b, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
-                if (fb && pv && hD && hU && rx_fh && ry_c && rp_c) err |= fb;
-            }
-            {
-                Face a = {}, b = {};
-                if (pv && hL && hR) {
-                    a = load_face_b(pp, wo, QLO(1, 0));
-                    b = load_face_b(pp, wo, QHI(1, 0));
-                }
-                const Flux dF2xz = getX(cz, 0, t);
-                yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
-                if (fb && pv && hL && hR && ry_f && rx_c && rp_c) err |= fb;
-                yh = final_state2(b, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
-                if (fb && pv && hL && hR && ry_fh && rx_c && rp_c) err |= fb;
-            }
-            putX(cz, 0, t, dxz);
-            putX(cz, 5, t, dyz);
-            __syncthreads();
-            // ------------------------------------------------ E/F: round-3 in-plane fluxes
-            putF(xa.v, 0, t, xh);
-            putF(xa.v, 5, t, yh);
-            __syncthreads();
-            const Flux F3x = hllc(getF(xa.v, 0, tL), xl, 0, gamma, igm1);
-            const Flux F3y = hllc(getF(xa.v, 5, tD), yl, 1, gamma, igm1);
-            putX(xb.v, 0, t, F3x);
-            putX(xb.v, 5, t, F3y);
-            __syncthreads();
-            // ------------------------------------------------ H: update plane p
-            if (outc && pv) {
-                const Flux Hx = getX(xb.v, 0, tR), Hy = getX(xb.v, 5, tU);
-                const double Fx[5][2] = {{F3x.m, Hx.m}, {F3x.mu, Hx.mu}, {F3x.mv, Hx.mv},
-                                         {F3x.mw, Hx.mw}, {F3x.e, Hx.e}};
-                const double Fy[5][2] = {{F3y.m, Hy.m}, {F3y.mu, Hy.mu}, {F3y.mv, Hy.mv},
-                                         {F3y.mw, Hy.mw}, {F3y.e, Hy.e}};
-                const Flux F3z = getX(cz, 10, t);
-                const double Fz[5][2] = {{F3z.m, F3zq.m}, {F3z.mu, F3zq.mu}, {F3z.mv, F3zq.mv},
-                                         {F3z.mw, F3zq.mw}, {F3z.e, F3zq.e}};
-                const unsigned bo = (unsigned)cell(g, x, y, p) * 8u;
-                double Uo[5], Us[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    double du = ax * (Fx[v][1] - Fx[v][0]);
-                    du = du + ay * (Fy[v][1] - Fy[v][0]);
-                    du = du + az * (Fz[v][1] - Fz[v][0]);
-                    Uo[v] = ldb(o.U + v * g.cs, bo);
-                    Us[v] = Uo[v] - du;
-                }
-                const double h = 0.5 * dt;
-                const double gg[3] = {gx, gy, gz};
-#pragma unroll
-                for (int e = 0; e < 3; ++e)
-                    if (gg[e] != 0.0) {
-                        double hg = h * gg[e];
-                        double mnew = Us[1 + e] + hg * (Uo[0] + Us[0]);
-                        Us[4] = Us[4] + hg * (Uo[1 + e] + mnew);
-                        Us[1 + e] = mnew;
-                    }
-                Prim qn = prim_of(Us[0], Us[1], Us[2], Us[3], Us[4], gm1);
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    if (!isfinite(Us[v])) err |= HYDRO_ERR_NONFINITE;
-                    *(double *)((char *)(o.Un + v * g.cs) + bo) = Us[v];
-                }
-                if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
-                if (qn.p <= 0.0) err |= HYDRO_ERR_P;
-                if (o.dtn) dtn = dmin(dtn, cfl_cell(qn, gamma, g.dx));
-            }
-            putX(cz, 10, t, F3zq);
-            __syncthreads();
         }
+        __syncthreads();
+        // ---------------------------------------------------- final states
+        // final z state of plane q
+        const Flux dyx = fdiff(getX(yb.v, 0, tU), getX(yb.v, 0, t));
+        const bool zin = hL && hR && hD && hU && rx_c && ry_c;
+        Face zl = final_state2(qz_lo, dxy, dyx, fx2, fy2, gm1, igm1, fb);
+        if (fb && zin && rz_f) err |= fb;
+        Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, igm1, fb);
+        if (fb && zin && rz_fh) err |= fb;
+        const Flux F3zq = hllc(fz_hi, zl, 2, gamma, igm1);
+        fz_hi = zh;
+        // y-difference of the (y|z) fluxes of plane q (used next plane)
+        const Flux dyz = fdiff(getX(yb.v, 5, tU), getX(yb.v, 5, t));
+        // final x and y states of plane q-1
+        const int p = q - 1;
+        const bool pv = p >= T.z0;  // plane p is finished in this segment
+        const bool rp_c = inr(p, 0, n2 - 1);
+        const char *pp = ws.plane(p);
+        Face xl, xh, yl, yh;
+        // (lanes whose final x or y states are never used skip reading
+        // their traced states: the ring rows for x, the ring columns for y,
+        // and every lane in a segment's warm-up plane)
+        {
+            Face a = {}, b = {};
+            if (pv && hD && hU) {
+                a = load_face_b(pp, wo, QLO(0, 0));
+                b = load_face_b(pp, wo, QHI(0, 0));
+            }
+            const Flux dF2yz = getX(cz, 5, t);
+            xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
+            if (fb && pv && hD && hU && rx_f && ry_c && rp_c) err |= fb;
+            xh = final_state2(b, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
+            if (fb && pv && hD && hU && rx_fh && ry_c && rp_c) err |= fb;
+        }
+        {
+            Face a = {}, b = {};
+            if (pv && hL && hR) {
+                a = load_face_b(pp, wo, QLO(1, 0));
+                b = load_face_b(pp, wo, QHI(1, 0));
+            }
+            const Flux dF2xz = getX(cz, 0, t);
+            yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
+            if (fb && pv && hL && hR && ry_f && rx_c && rp_c) err |= fb;
+            yh = final_state2(b, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
+            if (fb && pv && hL && hR && ry_fh && rx_c && rp_c) err |= fb;
+        }
+        putX(cz, 0, t, dxz);
+        putX(cz, 5, t, dyz);
+        // ---------------------------------------------------- round-3 in-plane fluxes
+        putF(ya.v, 0, t, yh);
+        // x: the low neighbour's high state from the neighbour lane; the
+        // flux difference over the cell, times dt/dx, right away
+        Flux dux;
+        {
+            const Flux d = next_minus(hllc(prevF(xh), xl, 0, gamma, igm1));
+            dux.m = ax * d.m;
+            dux.mu = ax * d.mu;
+            dux.mv = ax * d.mv;
+            dux.mw = ax * d.mw;
+            dux.e = ax * d.e;
+        }
+        __syncthreads();
+        putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), yl, 1, gamma, igm1));
+        __syncthreads();
+        // ---------------------------------------------------- update plane p
+        if (outc && pv) {
+            const Flux dy = fdiff(getX(yb.v, 0, tU), getX(yb.v, 0, t));
+            const Flux F3z = getX(cz, 10, t);
+            const double dxv[5] = {dux.m, dux.mu, dux.mv, dux.mw, dux.e};
+            const double dyv[5] = {dy.m, dy.mu, dy.mv, dy.mw, dy.e};
+            const double Fz[5][2] = {{F3z.m, F3zq.m}, {F3z.mu, F3zq.mu}, {F3z.mv, F3zq.mv},
+                                     {F3z.mw, F3zq.mw}, {F3z.e, F3zq.e}};
+            const unsigned bo = (unsigned)cell(g, x, y, p) * 8u;
+            double Uo[5], Us[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double du = dxv[v];
+                du = du + ay * dyv[v];
+                du = du + az * (Fz[v][1] - Fz[v][0]);
+                Uo[v] = ldb(o.U + v * g.cs, bo);
+                Us[v] = Uo[v] - du;
+            }
+            const double h = 0.5 * dt;
+            const double gg[3] = {gx, gy, gz};
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+                if (gg[e] != 0.0) {
+                    double hg = h * gg[e];
+                    double mnew = Us[1 + e] + hg * (Uo[0] + Us[0]);
+                    Us[4] = Us[4] + hg * (Uo[1 + e] + mnew);
+                    Us[1 + e] = mnew;
+                }
+            Prim qn = prim_of(Us[0], Us[1], Us[2], Us[3], Us[4], gm1);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                if (!isfinite(Us[v])) err |= HYDRO_ERR_NONFINITE;
+                *(double *)((char *)(o.Un + v * g.cs) + bo) = Us[v];
+            }
+            if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
+            if (qn.p <= 0.0) err |= HYDRO_ERR_P;
+            if (o.dtn) dtn = dmin(dtn, cfl_cell(qn, gamma, g.dx));
+        }
+        putX(cz, 10, t, F3zq);
     }
     if (err) atomicOr(err_dev, err);
-    // (the z-march ended on a barrier: the exchange buffers are free)
-    if (o.dtn) block_dt_min(dtn, cfl, o.dtn, L.dtn_min, xa.v[0]);
+    // (every lane has passed the z-march's last barrier, and the last reads
+    // of ya happened before it: ya is free)
+    if (o.dtn) block_dt_min(dtn, cfl, o.dtn, L.dtn_min, ya.v[0]);
 }
 
 }  // namespace
