@@ -67,6 +67,18 @@ __device__ __forceinline__ Face getF(double (*b)[kFT], int k0, int t)
     f.ri = 1.0 / f.r;
     return f;
 }
+// the same without forming 1/rho
+__device__ __forceinline__ Face getF_raw(double (*b)[kFT], int k0, int t)
+{
+    Face f;
+    f.r = b[k0 + 0][t];
+    f.u = b[k0 + 1][t];
+    f.v = b[k0 + 2][t];
+    f.w = b[k0 + 3][t];
+    f.p = b[k0 + 4][t];
+    f.ri = 0.0;
+    return f;
+}
 __device__ __forceinline__ Flux getX(double (*b)[kFT], int k0, int t)
 {
     Flux f;
@@ -203,7 +215,8 @@ __device__ __forceinline__ double dpp_next(double v)  // lane t+1's v
                                                false);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
-// the low x-neighbour's state, with 1/rho formed as its writer formed it
+// the low x-neighbour's state; its 1/rho is the neighbour's (formed there,
+// as 1/rho, by the state's primitive conversion or by with_ri)
 __device__ __forceinline__ Face prevF(const Face &f)
 {
     Face g;
@@ -212,7 +225,7 @@ __device__ __forceinline__ Face prevF(const Face &f)
     g.v = dpp_prev(f.v);
     g.w = dpp_prev(f.w);
     g.p = dpp_prev(f.p);
-    g.ri = 1.0 / g.r;
+    g.ri = dpp_prev(f.ri);
     return g;
 }
 // the high x-neighbour's flux minus this lane's
@@ -300,7 +313,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         const Flux F1zn = hllc(with_ri(qz_hi),
                                with_ri(load_face_b(ws.plane(q + 1), wo, QLO(2, 0))),  // next plane
                                2, gamma, igm1);
-        const Flux dF1x = next_minus(hllc(prevF(qx_hi), with_ri(qx_lo), 0, gamma, igm1));
+        const Flux dF1x = next_minus(hllc(prevF(with_ri(qx_hi)), with_ri(qx_lo), 0, gamma, igm1));
         __syncthreads();
         putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), with_ri(qy_lo), 1, gamma, igm1));
         // (the round-1 z-flux carried from the plane below is never used
@@ -416,6 +429,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         putX(cz, 5, t, dyz);
         // ---------------------------------------------------- round-3 in-plane fluxes
         putF(ya.v, 0, t, yh);
+        ya.v[5][t] = yh.ri;  // the upper neighbour takes yh with its 1/rho
         // x: the low neighbour's high state from the neighbour lane; the
         // flux difference over the cell, times dt/dx, right away
         Flux dux;
@@ -428,7 +442,11 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             dux.e = ax * d.e;
         }
         __syncthreads();
-        putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), yl, 1, gamma, igm1));
+        {
+            Face L = getF_raw(ya.v, 0, tD);
+            L.ri = ya.v[5][tD];
+            putX(yb.v, 0, t, hllc(L, yl, 1, gamma, igm1));
+        }
         __syncthreads();
         // ---------------------------------------------------- update plane p
         if (outc && pv) {
