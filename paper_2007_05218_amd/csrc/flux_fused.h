@@ -302,19 +302,21 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         // covers them)
         const bool rz_c = inr(q, 0, n2 - 1) && q >= T.z0, rz_w = inr(q, -1, n2);
         // ---------------------------------------------------- loads
+        // (the high y-state first: its exchange opens the z-step, and the
+        // other loads complete while the block meets at the barrier)
+        const Face qy_hi = load_face_b(pq, wo, QHI(1, 0));
+        putF(ya.v, 0, t, qy_hi);
         const Face qx_lo = load_face_b(pq, wo, QLO(0, 0)), qx_hi = load_face_b(pq, wo, QHI(0, 0));
-        const Face qy_lo = load_face_b(pq, wo, QLO(1, 0)), qy_hi = load_face_b(pq, wo, QHI(1, 0));
+        const Face qy_lo = load_face_b(pq, wo, QLO(1, 0));
         const Face qz_lo = load_face_b(pq, wo, QLO(2, 0)), qz_hi = load_face_b(pq, wo, QHI(2, 0));
+        const Face qz_lo_n = load_face_b(ws.plane(q + 1), wo, QLO(2, 0));  // next plane
+        __syncthreads();
         // ---------------------------------------------------- round-1 fluxes
         // through each lane's low x/y faces (the low neighbour's high state
         // from the neighbour lane: x in the wavefront, y through LDS) and
         // through the plane's high z-face; their differences over the cell
-        putF(ya.v, 0, t, qy_hi);
-        const Flux F1zn = hllc(with_ri(qz_hi),
-                               with_ri(load_face_b(ws.plane(q + 1), wo, QLO(2, 0))),  // next plane
-                               2, gamma, igm1);
+        const Flux F1zn = hllc(with_ri(qz_hi), with_ri(qz_lo_n), 2, gamma, igm1);
         const Flux dF1x = next_minus(hllc(prevF(with_ri(qx_hi)), with_ri(qx_lo), 0, gamma, igm1));
-        __syncthreads();
         putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), with_ri(qy_lo), 1, gamma, igm1));
         // (the round-1 z-flux carried from the plane below is never used
         // before the first plane's)
