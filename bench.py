@@ -45,12 +45,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rt512_traffic.json")
 KERNEL_SYMBOL = {"trace": "k_trace_fused", "flux_update": "k_flux_fused"}
 
 
+# the sources the profiled step kernels are built from
+STEP_SOURCES = ("flux_fused.h", "hydro.hip", "hydro_common.h", "trace_fused.h")
+
+
 def source_hash():
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2007_05218_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2007_05218_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
