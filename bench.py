@@ -17,7 +17,9 @@ Also reported on the same JSON line:
   cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
                 same workload (rank 0, N = 1 only)
   also          secondary workloads: the 256^3 Kelvin-Helmholtz box; the
-                512-box batched level (one launch per stage for all boxes)
+                paper's Sedov blast at its per-node size (256^3 as 64 boxes of
+                64^3 tiling the domain, with the ghost exchange between boxes,
+                and as one box); the 512-box batched level (one launch per stage for all boxes)
                 against the same boxes launched one by one; the serving loop
                 (p50/p99 latency and cell-updates/s at 80% load, and its
                 saturated capacity batched vs one request at a time)
@@ -83,8 +85,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="rt512,kh256,level,serve",
-                    help="comma list of rt512, kh256, level, serve, copy (a plain 2 GiB "
+    ap.add_argument("--workloads", default="rt512,kh256,sedov,level,serve",
+                    help="comma list of rt512, kh256, sedov, level, serve, copy (a plain 2 GiB "
                          "device copy, the reference for HBM traffic counters)")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-warmup", type=int, default=20)
@@ -185,6 +187,54 @@ def time_level(hydro, torch, inputs, steps, warmup):
             "per_box_cu_per_s": cells * steps / (ms_per_box * 1e-3),
             "batched_ms_per_step": ms_batched / steps, "per_box_ms_per_step": ms_per_box / steps,
             "autotune_s": tune_s, "tile_table": table}
+
+
+def time_sedov(hydro, torch, inputs, steps, warmup, n=256, bs=64):
+    """The paper's blast problem at its per-node size (Sec. IV-A: 256^3 cells
+    per node in 64^3 boxes): the domain as a tiled level of (n/bs)^3 boxes
+    (ghost exchange between boxes + batched advance), its ghost exchange on
+    its own, and the same domain advanced as one box."""
+    states, boxes, prm, lo, til = inputs.sedov_level(n, bs)
+    tiling = hydro.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    lev = hydro.Level(states, boxes, prm, shared_dt=True, tiling=tiling)
+    for _ in range(warmup):
+        lev.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        lev.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    e0.record()
+    for _ in range(steps):
+        hydro.fill_ghosts_level(tiling, lev.pa)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fill = e0.elapsed_time(e1) / steps
+    err = int(lev.err.item())
+    del lev
+    tiling.close()
+    torch.cuda.empty_cache()
+    ghosts = sum((b["n"][0] + 2 * b["ng"]) * (b["n"][1] + 2 * b["ng"]) * (b["n"][2] + 2 * b["ng"])
+                 - b["n"][0] * b["n"][1] * b["n"][2] for b in boxes)
+    U, box, _ = inputs.sedov(n)
+    ms1, _, _, err1 = time_box(hydro, torch, U, box, prm, steps, warmup)
+    cells = n ** 3
+    return {"workload": "sedov%d: point blast (rho 1, p 1e-5, E 1 in r < 2 dx), unit cube, "
+                        "outflow, gamma 1.4, CFL 0.5, as %d boxes of %d^3 tiling the domain"
+                        % (n, len(boxes), bs),
+            "cells": cells, "boxes": len(boxes), "steps": steps,
+            "tiled_cu_per_s": cells / (ms * 1e-3), "tiled_ms_per_step": ms,
+            "level_fill_ms": ms_fill,
+            "level_fill_GB_per_s": 80.0 * ghosts / (ms_fill * 1e-3) / 1e9,
+            "level_fill_bytes": 80 * ghosts,
+            "one_box_cu_per_s": cells / (ms1 / steps * 1e-3), "one_box_ms_per_step": ms1 / steps,
+            "err_bits": err | err1,
+            "paper_context": "Castro Sedov: 130 zones/us per Summit node (6 V100) at 256^3 "
+                             "cells per node in 64^3 boxes; about 25 zones/us per V100 under "
+                             "optimal conditions (other hardware, precision not stated)"}
 
 
 def time_serving(inputs, nreq, warm, seed=3):
@@ -319,6 +369,10 @@ def main():
         also["kh256"] = {"cu_per_s": n2 * args.steps / (ms2 * 1e-3),
                          "ms_per_step": ms2 / args.steps, "err": e2}
         del U2
+    if "sedov" in work:
+        log("timing the Sedov blast, 256^3 as 64 boxes of 64^3 and as one box")
+        also["sedov256"] = time_sedov(hydro, torch, inputs, args.steps, args.warmup)
+        log("sedov:", json.dumps(also["sedov256"]))
     if "level" in work:
         log("timing the 512-box level, batched vs per-box")
         also["level512"] = time_level(hydro, torch, inputs, args.level_steps, 1)

@@ -161,6 +161,36 @@ hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
 hydro_status hydro_fill_ghosts_boxes(int nb, double *const *U_ptrs_dev, const void *plan,
                                      void *stream);
 
+/* A level whose boxes tile one problem domain (Sec. II: a level's boxes
+ * cover the domain, and a box's stencil reads neighbour data from the boxes
+ * next to it).  boxes[b] (valid cells n, ghost depth ng) has its valid cell
+ * (0,0,0) at domain index lo[3b .. 3b+2]; the boxes must cover the
+ * dom[0] x dom[1] x dom[2] domain exactly, without overlap, and every ng
+ * must be <= each dom[d].  bc_lo/bc_hi are the domain's boundary kinds
+ * (periodic paired); the boxes' own bc fields are not used by the level.
+ * The owner map the level keeps has (D0/G)(D1/G)(D2/G) entries, G the
+ * greatest common divisor of all box corners, sides and domain sizes; more
+ * than 2^24 entries is HYDRO_EINVAL.  *level receives an opaque handle that
+ * owns one device buffer; HYDRO_EINVAL for an invalid or non-tiling layout,
+ * HYDRO_EHIP if the device buffer cannot be set up. */
+hydro_status hydro_level_create(const hydro_box *boxes, const int32_t *lo, int nb,
+                                const int32_t *dom, const int32_t *bc_lo,
+                                const int32_t *bc_hi, void **level);
+void hydro_level_destroy(void *level);
+
+/* Ghost exchange of a level (a FillBoundary analogue), one launch: every
+ * ghost cell of every box takes the value that the whole domain, held as one
+ * box with the level's boundary kinds and filled by hydro_fill_ghosts, has at
+ * the same domain index -- from the neighbouring box that owns it, across a
+ * periodic face, or by the outflow/reflect rule at a domain face.  Bitwise
+ * copies (reflection only negates).  U_ptrs_dev: device array of nb state
+ * pointers in the level's box order; states must not overlap.  With the
+ * timesteps that advance_boxes reduces, a stepping loop over a tiled domain
+ * is hydro_fill_ghosts_level + advance_boxes with the shared timestep, and
+ * every box's new valid cells equal the whole domain's advanced as one box. */
+hydro_status hydro_fill_ghosts_level(int nb, double *const *U_ptrs_dev, const void *level,
+                                     void *stream);
+
 /* Plan for a fixed list of boxes: validates them, chooses the tile shapes
  * (autotune_json: NULL for the built-in choice, else a JSON object mapping
  * box shapes "NXxNYxNZ" to [tbx, tzs] for both fused kernels or

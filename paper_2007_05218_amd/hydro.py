@@ -24,7 +24,8 @@ ERR_NONFINITE, ERR_RHO, ERR_P, ERR_FALLBACK = 1, 2, 4, 8
 EXPORTS = ("hydro_state_elems", "hydro_workspace_bytes", "hydro_fill_ghosts", "estimate_dt",
            "advance_box", "estimate_dt_boxes", "advance_boxes", "hydro_plan_create",
            "hydro_plan_destroy", "hydro_status_string", "hydro_stage_count",
-           "hydro_stage_name", "hydro_set_stage_events", "hydro_fill_ghosts_boxes")
+           "hydro_stage_name", "hydro_set_stage_events", "hydro_fill_ghosts_boxes",
+           "hydro_level_create", "hydro_level_destroy", "hydro_fill_ghosts_level")
 
 
 class HydroBox(C.Structure):
@@ -79,8 +80,14 @@ def lib():
         L.hydro_status_string.argtypes = [C.c_int]
         L.hydro_status_string.restype = C.c_char_p
         L.hydro_fill_ghosts_boxes.argtypes = [C.c_int, vp, vp, vp]
+        i3 = C.POINTER(C.c_int32)
+        L.hydro_level_create.argtypes = [bp, i3, C.c_int, i3, i3, i3, C.POINTER(vp)]
+        L.hydro_level_destroy.argtypes = [vp]
+        L.hydro_level_destroy.restype = None
+        L.hydro_fill_ghosts_level.argtypes = [C.c_int, vp, vp, vp]
         for f in ("hydro_fill_ghosts", "estimate_dt", "advance_box", "estimate_dt_boxes",
-                  "advance_boxes", "hydro_plan_create", "hydro_fill_ghosts_boxes"):
+                  "advance_boxes", "hydro_plan_create", "hydro_fill_ghosts_boxes",
+                  "hydro_level_create", "hydro_fill_ghosts_level"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -262,12 +269,59 @@ def fill_ghosts_boxes(plan, U_ptrs, stream=None):
         plan.nb, _ptr(U_ptrs, torch.int64), plan.handle, _stream(stream)))
 
 
-class Level:
-    """A list of independent boxes advanced together (a level of boxes): states
-    and workspace on the device, one launch per stage for all boxes.
-    ``shared_dt`` advances every box by the level-wide minimum timestep."""
+class Tiling:
+    """The boxes of a level tiling one domain (hydro_level_create): box b's
+    valid cell (0,0,0) sits at domain index ``lo[b]``; ``dom`` is the domain's
+    cell count and ``bc_lo``/``bc_hi`` its boundary kinds.  Owns one small
+    device buffer."""
 
-    def __init__(self, states, boxes, prm, shared_dt=True, device="cuda", autotune_json=None):
+    def __init__(self, boxes, lo, dom, bc_lo, bc_hi):
+        self.boxes = [dict(b) for b in boxes]
+        self.lo = [tuple(int(v) for v in l) for l in lo]
+        self.dom = tuple(int(v) for v in dom)
+        self.bc_lo, self.bc_hi = tuple(bc_lo), tuple(bc_hi)
+        arr = (HydroBox * len(boxes))(*[make_box(b) for b in boxes])
+        flat = (C.c_int32 * (3 * len(boxes)))(*[v for l in self.lo for v in l])
+        i3 = C.c_int32 * 3
+        h = C.c_void_p()
+        _check("hydro_level_create", lib().hydro_level_create(
+            arr, flat, len(boxes), i3(*self.dom), i3(*self.bc_lo), i3(*self.bc_hi),
+            C.byref(h)))
+        self.handle = h
+        self.nb = len(boxes)
+
+    def close(self):
+        if self.handle:
+            lib().hydro_level_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fill_ghosts_level(tiling, U_ptrs, stream=None):
+    """Ghost exchange between the boxes of a tiled level (one launch)."""
+    _check("hydro_fill_ghosts_level", lib().hydro_fill_ghosts_level(
+        tiling.nb, _ptr(U_ptrs, torch.int64), tiling.handle, _stream(stream)))
+
+
+class Level:
+    """A list of boxes advanced together (a level of boxes): states and
+    workspace on the device, one launch per stage for all boxes.
+    ``shared_dt`` advances every box by the level-wide minimum timestep.
+    Without ``tiling`` the boxes are independent (each fills its own ghosts
+    from its boundary kinds); with a ``Tiling`` of the same boxes they tile one
+    domain, the ghosts come from the neighbouring boxes (hydro_fill_ghosts_level)
+    and the timestep is shared."""
+
+    def __init__(self, states, boxes, prm, shared_dt=True, device="cuda", autotune_json=None,
+                 tiling=None):
+        if tiling is not None and (not shared_dt or tiling.nb != len(boxes)):
+            raise ValueError("a tiled level needs a tiling of its boxes and a shared timestep")
+        self.tiling = tiling
         self.prm = dict(prm)
         self.plan = Plan(boxes, autotune_json)
         self.U = [torch.as_tensor(u, dtype=torch.float64).to(device).contiguous() for u in states]
@@ -287,11 +341,16 @@ class Level:
         """Ghost fill + timesteps + advance of every box (the timesteps of
         states the previous step produced come from that step's advance)."""
         if self.have_dt:
-            fill_ghosts_boxes(self.plan, self.pa, stream)
+            if self.tiling is None:
+                fill_ghosts_boxes(self.plan, self.pa, stream)
             self.dt, self.dt_next = self.dt_next, self.dt
             self.dt_min, self.dt_next_min = self.dt_next_min, self.dt_min
         else:
+            # (the timestep reads valid cells only; its per-box ghost fill is
+            # replaced below for a tiled level)
             estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, self.dt_min, stream)
+        if self.tiling is not None:
+            fill_ghosts_level(self.tiling, self.pa, stream)
         if self.shared_dt:
             advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt_min, self.ws, self.err,
                           dt_stride=0, stream=stream, dt_next=self.dt_next,

@@ -17,6 +17,8 @@ inputs are not available; these synthetic families stand in for them):
            g = -0.1 z, seeded phase of a single-mode interface, reflecting z walls
   smooth   sum of seeded Fourier modes, periodic (the batched AMR-like level)
   advect   a smooth density wave carried by a uniform flow, periodic
+  sedov    point blast in the unit cube, outflow boundaries (the paper's
+           Sec. IV hydro benchmark problem), also as a domain tiled by boxes
 """
 import math
 
@@ -179,6 +181,71 @@ def uniform(n, rho=1.0, vel=(0.3, -0.2, 0.1), p=1.0, bc=BC_PERIODIC, ng=NG):
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     box = box_desc(nn, ng, bc_lo=(bc,) * 3)
     return from_primitive(box, rho, vel[0], vel[1], vel[2], p), box, params_desc()
+
+
+def sedov(n=64, r0_cells=2.0, p_amb=1e-5, e_blast=1.0, ng=NG):
+    """Point blast (Sedov-Taylor) in the unit cube: rho = 1, at rest, pressure
+    p_amb, except the cells whose centres lie within r0_cells cell widths of
+    the cube's centre, which share the energy e_blast evenly as pressure
+    (p = (gamma - 1) e_blast / deposited volume); outflow on all faces."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    box = box_desc(nn, ng, bc_lo=(BC_OUTFLOW,) * 3)
+    x, y, z = cell_centres(box)
+    shp = (nn[2], nn[1], nn[0])
+    r = np.broadcast_to(np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2), shp)
+    dep = r < r0_cells * min(box["dx"])
+    vol = dep.sum() * box["dx"][0] * box["dx"][1] * box["dx"][2]
+    p = np.where(dep, (GAMMA - 1.0) * e_blast / vol, p_amb)
+    return from_primitive(box, 1.0, 0.0, 0.0, 0.0, p), box, params_desc()
+
+
+# ---------------------------------------------------------------------------
+# a domain split into boxes that tile it
+# ---------------------------------------------------------------------------
+
+def tile(U, box, cuts):
+    """Split the state U of a domain box into boxes that tile it: ``cuts[d]``
+    lists the cut positions along axis d (first 0, last n_d).  Returns
+    (states, boxes, lo, tiling): box states with zero ghost cells, box
+    descriptions (the domain's cell widths and ghost depth; their own
+    boundary kinds, periodic or outflow for boxes thinner than the ghost
+    depth, are not the domain's), each box's lower corner, and the
+    arguments of a tiling (dom, bc_lo, bc_hi)."""
+    n, ng = box["n"], box["ng"]
+    for d in range(3):
+        c = list(cuts[d])
+        if c[0] != 0 or c[-1] != n[d] or any(b <= a for a, b in zip(c, c[1:])):
+            raise ValueError("cuts must increase from 0 to n along every axis")
+    V = valid(U, box)
+    states, boxes, lo = [], [], []
+    for k0, k1 in zip(cuts[2], cuts[2][1:]):
+        for j0, j1 in zip(cuts[1], cuts[1][1:]):
+            for i0, i1 in zip(cuts[0], cuts[0][1:]):
+                nb = (i1 - i0, j1 - j0, k1 - k0)
+                bc = tuple(BC_PERIODIC if m >= ng else BC_OUTFLOW for m in nb)
+                b = box_desc(nb, ng, dx=box["dx"], bc_lo=bc)
+                W = np.zeros(state_shape(b))
+                valid(W, b)[...] = V[:, k0:k1, j0:j1, i0:i1]
+                states.append(W)
+                boxes.append(b)
+                lo.append((i0, j0, k0))
+    return states, boxes, lo, {"dom": tuple(n), "bc_lo": box["bc_lo"], "bc_hi": box["bc_hi"]}
+
+
+def even_cuts(n, bs):
+    """Cuts of n cells into boxes of bs cells (the last one shorter if bs does
+    not divide n)."""
+    return list(range(0, n, bs)) + [n]
+
+
+def sedov_level(n=256, bs=64, ng=NG):
+    """The Sedov blast on an n^3 domain held as (n/bs)^3 boxes of bs^3 cells
+    (the paper's per-node Sedov runs use 64^3 boxes, Sec. IV-A).  Returns
+    (states, boxes, params, lo, tiling arguments)."""
+    U, box, prm = sedov(n, ng=ng)
+    c = even_cuts(n, bs)
+    states, boxes, lo, til = tile(U, box, (c, c, c))
+    return states, boxes, prm, lo, til
 
 
 # ---------------------------------------------------------------------------

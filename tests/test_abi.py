@@ -135,3 +135,44 @@ def test_autotune_table_format():
     assert js == '{"16x32x64": [16, 32], "64x64x64": [32, 64, 16, 32]}'
     c = autotune.candidates((16, 32, 64))
     assert (8, 64) in c and (32, 8) in c and all(t[0] in (8, 16, 32) for t in c)
+
+
+def _level_args(layout):
+    """(boxes, lo, dom, bc_lo, bc_hi) of a tiling, possibly broken."""
+    boxes = [inputs.box_desc(n) for n in layout["n"]]
+    return boxes, layout["lo"], layout["dom"], layout.get("bc_lo", (0, 0, 0)), \
+        layout.get("bc_hi", layout.get("bc_lo", (0, 0, 0)))
+
+
+GOOD = {"n": [(8, 16, 16), (8, 16, 16)], "lo": [(0, 0, 0), (8, 0, 0)], "dom": (16, 16, 16)}
+
+
+@pytest.mark.parametrize("bad", [
+    dict(lo=[(0, 0, 0), (4, 0, 0)]),                      # overlap (and a gap)
+    dict(n=[(8, 16, 16), (4, 16, 16)], lo=[(0, 0, 0), (8, 0, 0)]),  # gap
+    dict(lo=[(0, 0, 0), (9, 0, 0)]),                      # box beyond the domain
+    dict(lo=[(0, 0, 0), (-8, 0, 0)]),                     # negative corner
+    dict(dom=(16, 16, 0)),
+    dict(bc_lo=(0, 1, 1), bc_hi=(1, 1, 1)),               # unpaired periodic
+    dict(bc_lo=(0, 4, 0), bc_hi=(0, 4, 0)),               # unknown boundary kind
+    dict(n=[(1, 16, 16), (2, 16, 16)], lo=[(0, 0, 0), (1, 0, 0)], dom=(3, 16, 16)),  # ng > dom
+    # owner map beyond 2^24 cells (no common divisor > 1)
+    dict(n=[(257, 256, 256)], lo=[(0, 0, 0)], dom=(257, 256, 256)),
+])
+def test_level_rejects_bad_tilings(bad):
+    # validated before any device allocation, so no GPU is needed
+    lay = dict(GOOD)
+    lay.update(bad)
+    boxes, lo, dom, bl, bh = _level_args(lay)
+    if bad.get("dom") == (3, 16, 16):
+        boxes = [inputs.box_desc(n, bc_lo=(1, 1, 1)) for n in lay["n"]]
+    L = hydro.lib()
+    arr = (hydro.HydroBox * len(boxes))(*[hydro.make_box(b) for b in boxes])
+    flat = (C.c_int32 * (3 * len(boxes)))(*[v for l in lo for v in l])
+    i3 = C.c_int32 * 3
+    h = C.c_void_p(123)
+    assert L.hydro_level_create(arr, flat, len(boxes), i3(*dom), i3(*bl), i3(*bh),
+                                C.byref(h)) == hydro.HYDRO_EINVAL
+    assert h.value is None
+    # a null handle and a mismatched box count are refused by the fill
+    assert L.hydro_fill_ghosts_level(1, C.c_void_p(8), None, None) == hydro.HYDRO_EINVAL
