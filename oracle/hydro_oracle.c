@@ -243,8 +243,9 @@ static double mc_slope(double am, double a0, double ap)
     return 0.0;
 }
 
-/* limited face values (aL at i-1/2, aR at i+1/2) of cell i from a[i-2..i+2] */
-static void ppm_faces(const double a[5], double *aLo, double *aRo)
+/* limited face values (aL at i-1/2, aR at i+1/2) of cell i from a[i-2..i+2];
+ * f is the cell's shock-flattening coefficient (1: none) */
+static void ppm_faces(const double a[5], double f, double *aLo, double *aRo)
 {
     double dm = mc_slope(a[0], a[1], a[2]); /* slope of cell i-1 */
     double d0 = mc_slope(a[1], a[2], a[3]); /* slope of cell i   */
@@ -253,6 +254,13 @@ static void ppm_faces(const double a[5], double *aLo, double *aRo)
     double aL = 0.5 * (a[1] + a[2]) - (d0 - dm) * C6;
     double aR = 0.5 * (a[2] + a[3]) - (dp - d0) * C6;
     double ac = a[2];
+    /* shock flattening (Colella & Woodward 1984, Sec. 4): near a strong
+     * shock the interface values move toward the cell average, by the
+     * coefficient f, before the limiter */
+    if (f < 1.0) {
+        aL = f * aL + (1.0 - f) * ac;
+        aR = f * aR + (1.0 - f) * ac;
+    }
     /* Colella-Woodward parabola limiter */
     if ((aR - ac) * (ac - aL) <= 0.0) {
         aL = ac;
@@ -273,7 +281,51 @@ static void ppm_faces(const double a[5], double *aLo, double *aRo)
 
 void orc_ppm_parabola(const double a5[5], double out[2])
 {
-    ppm_faces(a5, &out[0], &out[1]);
+    ppm_faces(a5, 1.0, &out[0], &out[1]);
+}
+
+void orc_ppm_parabola_flat(const double a5[5], double f, double out[2])
+{
+    ppm_faces(a5, f, &out[0], &out[1]);
+}
+
+/* ------------------------------------------------------------------ */
+/* shock flattening (Colella & Woodward 1984, Sec. 4)                  */
+/* ------------------------------------------------------------------ */
+
+/* Along one axis, cell i is in a shock when the flow converges there
+ * (u[i-1] - u[i+1] > 0) and the pressure jumps across it by more than
+ * FL_EPS of the smaller neighbouring pressure; its steepness measure
+ * z = |p[i+1]-p[i-1]| / |p[i+2]-p[i-2]| (near 1/2 in a smooth profile, near
+ * 1 in a shock spread over two cells) gives chi = clamp(FL_W2 (z - FL_W1),
+ * 0, 1) there, 0 elsewhere.  The cell's coefficient along the axis is
+ * 1 - max(chi[i], chi[i+s]), where s points to the lower-pressure side
+ * (s = -1 when p[i+1] > p[i-1], else +1): a cell next to a shock on its
+ * high-pressure side -- the gas the shock has just passed -- is flattened
+ * with it. */
+#define FL_W1 0.75
+#define FL_W2 10.0
+#define FL_EPS 0.33
+#define FL_TINY 1e-300
+
+/* chi of the centre of p5[0..4], u3[0..2] (cells i-2..i+2 and i-1..i+1) */
+static double flat_chi(const double p5[5], const double u3[3])
+{
+    double dp = p5[3] - p5[1];
+    double dp2 = p5[4] - p5[0];
+    double z = fabs(dp) / mx(fabs(dp2), FL_TINY);
+    double chi = mn(1.0, mx(0.0, FL_W2 * (z - FL_W1)));
+    int shock = (u3[0] - u3[2] > 0.0) && (fabs(dp) > FL_EPS * mn(p5[3], p5[1]));
+    return shock ? chi : 0.0;
+}
+
+double orc_flatten_1d(const double p7[7], const double un7[7])
+{
+    /* chi of cells i-1, i, i+1 */
+    double chi[3];
+    for (int m = 0; m < 3; ++m) chi[m] = flat_chi(&p7[m], &un7[m + 1]);
+    int s = p7[4] > p7[2] ? -1 : 1;
+    return 1.0 - mx(chi[1], chi[1 + s]);
 }
 
 /* average of the parabola over the part of the cell swept by a wave of speed
@@ -299,7 +351,7 @@ void orc_ppm_integrals(const double a5[5], double lam, double dtdx, double *Ip,
                        double *Im)
 {
     double aL, aR;
-    ppm_faces(a5, &aL, &aR);
+    ppm_faces(a5, 1.0, &aL, &aR);
     *Ip = edge_hi(a5[2], aL, aR, lam, dtdx);
     *Im = edge_lo(a5[2], aL, aR, lam, dtdx);
 }
@@ -324,7 +376,7 @@ static void transverse(int d, int *t1, int *t2)
  * alpha = l_nu . (ref - I_nu), l_nu the left eigenvector of the primitive
  * system; the face state is ref - sum_nu alpha_nu r_nu.  The low face is the
  * mirror image with the - wave as reference and lam < 0. */
-static void trace_cell(const double q[5][5], double c, int d, double dtdx,
+static void trace_cell(const double q[5][5], double c, int d, double dtdx, double flat,
                        double qhi[5], double qlo[5])
 {
     int t1, t2;
@@ -339,7 +391,7 @@ static void trace_cell(const double q[5][5], double c, int d, double dtdx,
     for (int v = 0; v < 5; ++v) {
         double a[5];
         for (int m = 0; m < 5; ++m) a[m] = q[m][var[v]];
-        ppm_faces(a, &aL[v], &aR[v]);
+        ppm_faces(a, flat, &aL[v], &aR[v]);
         ac[v] = a[2];
     }
 #define IP(v, nu) edge_hi(ac[v], aL[v], aR[v], lam[nu], dtdx)
@@ -391,7 +443,7 @@ void orc_trace(const double q5[5][5], int d, double gamma, double dtdx,
                double qhi[5], double qlo[5])
 {
     double c = sqrt((gamma * q5[2][4]) * (1.0 / q5[2][0]));
-    trace_cell(q5, c, d, dtdx, qhi, qlo);
+    trace_cell(q5, c, d, dtdx, 1.0, qhi, qlo);
 }
 
 /* ------------------------------------------------------------------ */
@@ -553,16 +605,21 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
     int err = 0;
     int rc = 0;
 
+    /* shock flattening reads pressures four cells out */
+    const int flat = pr->flatten;
+    if (flat < 0 || flat > 2 || (flat == 1 && ng < 4)) return -1;
+    const int pw = flat == 1 ? 4 : 3;
     int g3lo[3], g3hi[3], g1lo[3], g1hi[3];
     for (int d = 0; d < 3; ++d) {
-        g3lo[d] = lo[d] - 3;
-        g3hi[d] = hi[d] + 3;
+        g3lo[d] = lo[d] - pw;
+        g3hi[d] = hi[d] + pw;
         g1lo[d] = lo[d] - 1;
         g1hi[d] = hi[d] + 1;
     }
 
-    fld prim, qhi[3], qlo[3], F1[3], F2[3][3], F3[3];
+    fld prim, fl, qhi[3], qlo[3], F1[3], F2[3][3], F3[3];
     memset(&prim, 0, sizeof prim);
+    memset(&fl, 0, sizeof fl);
     memset(qhi, 0, sizeof qhi);
     memset(qlo, 0, sizeof qlo);
     memset(F1, 0, sizeof F1);
@@ -578,6 +635,30 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
         prim_c(Uc, gamma, gm1, fat(&prim, p));
     })
     ORC_STAGE_MARK(1);
+
+    /* shock-flattening coefficient of every traced cell: the smallest of
+     * its three axes' coefficients */
+    if (flat) {
+        if (!fld_make(&fl, g1lo, g1hi, 1)) { rc = -2; goto done; }
+        FOR_REGION(g1lo, g1hi, p, {
+            double f = 1.0;
+            if (flat == 2) {
+                f = 0.0;
+            } else {
+                for (int d = 0; d < 3; ++d) {
+                    double p7[7], un7[7];
+                    for (int m = 0; m < 7; ++m) {
+                        int r[3] = {p[0], p[1], p[2]};
+                        r[d] += m - 3;
+                        p7[m] = fat(&prim, r)[4];
+                        un7[m] = fat(&prim, r)[1 + d];
+                    }
+                    f = mn(f, orc_flatten_1d(p7, un7));
+                }
+            }
+            fat(&fl, p)[0] = f;
+        })
+    }
 
     /* A3 + A4: traced states at both faces of every cell, each direction,
      * on the cells one beyond the output region; then the half-step
@@ -598,7 +679,7 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
             }
             double c = fat(&prim, p)[5];
             double *hiq = fat(&qhi[d], p), *loq = fat(&qlo[d], p);
-            trace_cell(q5, c, d, dtdx, hiq, loq);
+            trace_cell(q5, c, d, dtdx, flat ? fat(&fl, p)[0] : 1.0, hiq, loq);
             for (int e = 0; e < 3; ++e)
                 if (pr->grav[e] != 0.0) {
                     hiq[1 + e] = hiq[1 + e] + (0.5 * dt) * pr->grav[e];
@@ -739,6 +820,7 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
 
 done:
     free(prim.v);
+    free(fl.v);
     for (int d = 0; d < 3; ++d) {
         free(qhi[d].v);
         free(qlo[d].v);

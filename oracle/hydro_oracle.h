@@ -61,6 +61,8 @@ typedef struct {
     double gamma;   /* ratio of specific heats, > 1 */
     double cfl;     /* Courant number, 0 < cfl <= 1 */
     double grav[3]; /* constant gravitational acceleration */
+    int flatten;    /* shock flattening: 0 off, 1 on (needs ng >= 4), 2 full
+                       flattening of every cell (coefficient 0; a test mode) */
 } orc_params;
 
 /* Number of doubles of one state array (all five components, with ghosts). */
@@ -96,6 +98,14 @@ int orc_advance_box(const double *U, double *Unew, const orc_box *b,
 /* Limited PPM parabola of cell i from a[i-2..i+2] (a5[0..4]):
  * out[0] = a_L (value at the low face), out[1] = a_R (high face). */
 void orc_ppm_parabola(const double a5[5], double out[2]);
+
+/* The same with the shock-flattening coefficient f of the cell (1: none). */
+void orc_ppm_parabola_flat(const double a5[5], double f, double out[2]);
+
+/* Shock-flattening coefficient of the centre cell of a 7-cell pencil along
+ * one axis: p7[m], un7[m] = pressure and velocity along the axis of cell
+ * i+m-3.  1 means no flattening. */
+double orc_flatten_1d(const double p7[7], const double un7[7]);
 
 /* Averages of the cell's parabola over the domain of dependence of a wave of
  * speed lam over dtdx = dt/dx: *Ip toward the high face, *Im toward the low

@@ -21,7 +21,8 @@ class OrcBox(C.Structure):
 
 
 class OrcParams(C.Structure):
-    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("grav", C.c_double * 3)]
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("grav", C.c_double * 3),
+                ("flatten", C.c_int)]
 
 
 _lib = None
@@ -70,13 +71,16 @@ def _load(path):
         L.orc_advance_region.argtypes = [dp, dp, bp, pp, C.c_double, ip, ip, ip]
         L.orc_advance_box.argtypes = [dp, dp, bp, pp, C.c_double, ip]
         L.orc_ppm_parabola.argtypes = [dp, dp]
+        L.orc_ppm_parabola_flat.argtypes = [dp, C.c_double, dp]
+        L.orc_flatten_1d.argtypes = [dp, dp]
+        L.orc_flatten_1d.restype = C.c_double
         L.orc_ppm_integrals.argtypes = [dp, C.c_double, C.c_double, dp, dp]
         L.orc_trace.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_hllc.argtypes = [dp, dp, C.c_int, C.c_double, dp]
         L.orc_prim_of_cons.argtypes = [dp, C.c_double, dp]
         L.orc_cons_of_prim.argtypes = [dp, C.c_double, dp]
         L.orc_num_threads.restype = C.c_int
-        for f in ("orc_ppm_parabola", "orc_ppm_integrals", "orc_trace", "orc_hllc",
+        for f in ("orc_ppm_parabola", "orc_ppm_parabola_flat", "orc_ppm_integrals", "orc_trace", "orc_hllc",
                   "orc_prim_of_cons", "orc_cons_of_prim"):
             getattr(L, f).restype = None
         return L
@@ -102,12 +106,12 @@ def box_from(desc):
     return make_box(desc["n"], desc["ng"], desc["dx"], desc["bc_lo"], desc["bc_hi"])
 
 
-def make_params(gamma=1.4, cfl=0.5, grav=(0.0, 0.0, 0.0)):
-    return OrcParams(gamma, cfl, (C.c_double * 3)(*grav))
+def make_params(gamma=1.4, cfl=0.5, grav=(0.0, 0.0, 0.0), flatten=0):
+    return OrcParams(gamma, cfl, (C.c_double * 3)(*grav), flatten)
 
 
 def params_from(desc):
-    return make_params(desc["gamma"], desc["cfl"], desc["grav"])
+    return make_params(desc["gamma"], desc["cfl"], desc["grav"], desc.get("flatten", 0))
 
 
 def fill_ghosts(U, box):
@@ -176,6 +180,20 @@ def ppm_parabola(a5):
     out = np.zeros(2)
     lib().orc_ppm_parabola(_dp(a), _dp(out))
     return out[0], out[1]
+
+
+def ppm_parabola_flat(a5, f):
+    a = np.ascontiguousarray(a5, dtype=np.float64)
+    out = np.zeros(2)
+    lib().orc_ppm_parabola_flat(_dp(a), f, _dp(out))
+    return out[0], out[1]
+
+
+def flatten_1d(p7, un7):
+    """Shock-flattening coefficient of the centre of a 7-cell pencil."""
+    p = np.ascontiguousarray(p7, dtype=np.float64)
+    u = np.ascontiguousarray(un7, dtype=np.float64)
+    return lib().orc_flatten_1d(_dp(p), _dp(u))
 
 
 def ppm_integrals(a5, lam, dtdx):

@@ -41,8 +41,10 @@ def box_desc(n, ng=NG, dx=None, bc_lo=(BC_PERIODIC,) * 3, bc_hi=None):
             "bc_lo": tuple(int(v) for v in bc_lo), "bc_hi": tuple(int(v) for v in bc_hi)}
 
 
-def params_desc(gamma=GAMMA, cfl=CFL, grav=(0.0, 0.0, 0.0)):
-    return {"gamma": float(gamma), "cfl": float(cfl), "grav": tuple(float(g) for g in grav)}
+def params_desc(gamma=GAMMA, cfl=CFL, grav=(0.0, 0.0, 0.0), flatten=0):
+    """Method parameters; ``flatten`` = 1 switches shock flattening on."""
+    return {"gamma": float(gamma), "cfl": float(cfl), "grav": tuple(float(g) for g in grav),
+            "flatten": int(flatten)}
 
 
 def state_shape(box):

@@ -1,7 +1,8 @@
 """The pins catch plausible mistakes: each mutant below is the oracle's source
 with one deliberate error (a flipped sign, a dropped term, a wrong constant
 or operand), compiled on the CPU; the battery of pins of
-test_oracle_pieces.py / test_oracle_scheme.py is run against it and at least
+test_oracle_pieces.py / test_oracle_scheme.py / test_oracle_flatten.py is run
+against it and at least
 one pin must fail.  Nothing here touches a GPU."""
 import os
 import subprocess
@@ -9,6 +10,7 @@ import tempfile
 
 import pytest
 
+import test_oracle_flatten as F
 import test_oracle_pieces as P
 import test_oracle_scheme as S
 
@@ -61,6 +63,18 @@ MUTANTS = {
     "corner coupling factor dt/2 for dt/3": (
         "const double fac = dt / (3.0 * b->dx[sd]);",
         "const double fac = dt / (2.0 * b->dx[sd]);"),
+    "flattening reaches toward the higher pressure": (
+        "int s = p7[4] > p7[2] ? -1 : 1;",
+        "int s = p7[4] > p7[2] ? 1 : -1;"),
+    "flattening without the compression test": (
+        "int shock = (u3[0] - u3[2] > 0.0) && (fabs(dp) > FL_EPS * mn(p5[3], p5[1]));",
+        "int shock = fabs(dp) > FL_EPS * mn(p5[3], p5[1]);"),
+    "flattening weights swapped": (
+        "aL = f * aL + (1.0 - f) * ac;",
+        "aL = (1.0 - f) * aL + f * ac;"),
+    "flattening steepness threshold": (
+        "double chi = mn(1.0, mx(0.0, FL_W2 * (z - FL_W1)));",
+        "double chi = mn(1.0, mx(0.0, FL_W2 * (z - 0.5)));"),
 }
 
 # the pins, cheapest first; each raises AssertionError when it fails
@@ -88,6 +102,10 @@ BATTERY = [
     ("Sod exact", lambda o: S.test_sod_against_exact_solution(o)),
     ("smooth order 2-D", lambda o: S.test_smooth_advection_second_order_2d(o)),
     ("smooth order 3-D", lambda o: S.test_smooth_advection_second_order_3d(o)),
+    ("flattening coefficient", lambda o: F.test_coefficient_worked_examples(o)),
+    ("flattening toward the mean", lambda o: F.test_flattening_limits_the_parabola_toward_the_mean(o)),
+    ("full flattening first order", lambda o: F.test_full_flattening_is_first_order(o)),
+    ("strong shock marked", lambda o: F.test_coefficient_marks_a_strong_shock_only(o)),
 ]
 
 
