@@ -82,9 +82,15 @@ typedef struct hydro_box {
 
 /* Physical and numerical parameters. */
 typedef struct hydro_params {
-    double gamma;   /* ratio of specific heats, > 1                    */
-    double cfl;     /* Courant number, 0 < cfl <= 1                    */
-    double grav[3]; /* constant gravitational acceleration (lab axes)  */
+    double gamma;    /* ratio of specific heats, > 1                    */
+    double cfl;      /* Courant number, 0 < cfl <= 1                    */
+    double grav[3];  /* constant gravitational acceleration (lab axes)  */
+    int32_t flatten; /* shock flattening of the PPM parabolae (Colella &
+                        Woodward 1984, Sec. 4; the paper's Castro hydro
+                        uses it for its Sedov runs): 0 off, 1 on.  On needs
+                        ng >= 4 in every box advanced (HYDRO_EINVAL
+                        otherwise); where no cell meets the shock test the
+                        results are bitwise those with it off            */
 } hydro_params;
 
 /* Doubles in one state array of `box` (all five components, with ghosts);

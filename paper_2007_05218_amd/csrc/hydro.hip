@@ -63,7 +63,7 @@ constexpr int kFields = 30;
 constexpr int kXB = 16;  // cells of an x-block of the workspace
 
 // stages (block-count prefix arrays are kept per stage)
-enum { ST_FILL = 0, ST_DT = 1, ST_TRACE = 2, ST_FLUX = 3, ST_COUNT = 4 };
+enum { ST_FILL = 0, ST_DT = 1, ST_TRACE = 2, ST_FLUX = 3, ST_FLAT = 4, ST_COUNT = 5 };
 constexpr int kDtCellsPerThread = 4;
 constexpr long long kDtMaxBlocks = 4096;
 
@@ -92,6 +92,13 @@ __host__ __device__ __forceinline__ int ws_xblocks(int n0) { return (n0 + 2 + kX
 __host__ __device__ __forceinline__ long long ws_pitch(int n0, int n1)  // bytes per plane
 {
     return (long long)(n1 + 2) * ws_xblocks(n0) * (kFields * kXB * 8);
+}
+// After the traced states, the workspace holds the shock-flattening
+// coefficient of every traced cell (x in [-1, n0], y in [-1, n1],
+// z in [-1, n2], x fastest), used only when flattening is on.
+__host__ __device__ __forceinline__ long long ws_flat_off(int n0, int n1, int n2)  // bytes
+{
+    return (ws_pitch(n0, n1) * (n2 + 4) + 255) / 256 * 256;
 }
 struct WS {
     char *base;        // plane z = -2
@@ -153,6 +160,8 @@ __host__ inline long long stage_blocks(const Geo &g, int st)
                ((g.n[2] + g.tzs2 - 1) / g.tzs2);
     }
     const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
+    if (st == ST_FLAT)  // one thread per traced cell
+        return ((long long)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2) + kBlock - 1) / kBlock;
     long long items = st == ST_FILL ? g.cs - nv : nv;
     if (st == ST_DT) {
         long long b = (items + (long long)kBlock * kDtCellsPerThread - 1) /
@@ -198,6 +207,7 @@ struct Box1 {
     long long blk;    // block index within the box
     long long nblk;   // blocks of this box in this stage
     unsigned long long *dtn;  // this box's next-step timestep (bit pattern), or null
+    double *flat;             // this box's flattening coefficients (workspace), or null
 };
 
 __device__ __forceinline__ Box1 resolve(const Launch &L)
@@ -233,6 +243,8 @@ __device__ __forceinline__ Box1 resolve(const Launch &L)
     o.dtn = L.dtn ? L.dtn + o.b : nullptr;
     o.ws.pitch = ws_pitch(o.g.n[0], o.g.n[1]);
     o.ws.nxb = ws_xblocks(o.g.n[0]);
+    o.flat = o.ws.base ? (double *)(o.ws.base + ws_flat_off(o.g.n[0], o.g.n[1], o.g.n[2]))
+                       : nullptr;
     return o;
 }
 
@@ -376,6 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
     block_dt_min(m, cfl, dt_bits + o.b, dtmin_bits, part);
 }
 
+#include "flatten.h"
 #include "flux_fused.h"
 #include "trace_fused.h"
 
@@ -405,7 +418,17 @@ bool box_valid(const hydro_box *b)
 bool params_valid(const hydro_params *p)
 {
     return p && p->gamma > 1.0 && isfinite(p->gamma) && p->cfl > 0.0 && p->cfl <= 1.0 &&
-           isfinite(p->grav[0]) && isfinite(p->grav[1]) && isfinite(p->grav[2]);
+           isfinite(p->grav[0]) && isfinite(p->grav[1]) && isfinite(p->grav[2]) &&
+           (p->flatten == 0 || p->flatten == 1);
+}
+
+// flattening reads pressures four cells out: every box needs four ghost layers
+bool flatten_ok(const hydro_params *p, const hydro_box *boxes, int nb)
+{
+    if (!p->flatten) return true;
+    for (int b = 0; b < nb; ++b)
+        if (boxes[b].ng < 4) return false;
+    return true;
 }
 
 // Built-in tile choice for the fused kernels when no tuned table applies
@@ -451,8 +474,8 @@ Geo make_geo(const hydro_box *b)
 
 size_t box_ws_bytes(const Geo &g)
 {
-    size_t bytes = (size_t)ws_pitch(g.n[0], g.n[1]) * (size_t)(g.n[2] + 4);
-    return (bytes + 255) / 256 * 256;
+    const size_t flat = (size_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2) * sizeof(double);
+    return (size_t)ws_flat_off(g.n[0], g.n[1], g.n[2]) + (flat + 255) / 256 * 256;
 }
 
 Launch single(const Geo &g, const double *U, double *Un, void *ws, const double *dt)
@@ -496,8 +519,14 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
         return dim3((unsigned)grid[stage]);
     };
     prof(PG_TRACE, 0, st);
-    hipLaunchKernelGGL(k_trace_fused, set(ST_TRACE), dim3(kTT), 0, st, L, gamma, prm->grav[0],
-                       prm->grav[1], prm->grav[2]);
+    if (prm->flatten) {
+        hipLaunchKernelGGL(k_flatten, set(ST_FLAT), dim3(kBlock), 0, st, L, gamma);
+        hipLaunchKernelGGL(k_trace_fused<true>, set(ST_TRACE), dim3(kTT), 0, st, L, gamma,
+                           prm->grav[0], prm->grav[1], prm->grav[2]);
+    } else {
+        hipLaunchKernelGGL(k_trace_fused<false>, set(ST_TRACE), dim3(kTT), 0, st, L, gamma,
+                           prm->grav[0], prm->grav[1], prm->grav[2]);
+    }
     prof(PG_TRACE, 1, st);
     prof(PG_FUSED, 0, st);
     hipLaunchKernelGGL(k_flux_fused, set(ST_FLUX), dim3(kFT), 0, st, L, gamma, prm->cfl,
@@ -663,7 +692,7 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
                          void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream)
 {
     if (!U_dev || !U_new_dev || !dt_dev || !ws_dev || !err_dev || !box_valid(box) ||
-        !params_valid(prm))
+        !params_valid(prm) || !flatten_ok(prm, box, 1))
         return HYDRO_EINVAL;
     if (dt_next_dev && overlaps(dt_next_dev, sizeof(double), dt_dev, sizeof(double)))
         return HYDRO_EINVAL;
@@ -809,7 +838,7 @@ hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
     const Plan *P = (const Plan *)plan;
     if (!P || nb != P->nb || !U_ptrs_dev || !U_new_ptrs_dev || !dt_dev || !ws_dev ||
         !err_dev || !params_valid(prm) || (dt_stride != 0 && dt_stride != 1) ||
-        (dt_next_min_dev && !dt_next_dev))
+        (dt_next_min_dev && !dt_next_dev) || !flatten_ok(prm, P->boxes.data(), P->nb))
         return HYDRO_EINVAL;
     {  // the next-step timesteps must not overlap the ones in use or each other
         const size_t ndt = (dt_stride ? (size_t)nb : 1) * sizeof(double);

@@ -96,12 +96,26 @@ __device__ __forceinline__ double ppm_iface(double al, double ar, double sl, dou
 // values aL (low face) and aR (high face)
 __device__ __forceinline__ Parab ppm_limit(double a2, double aL, double aR);
 
-__device__ __forceinline__ Parab ppm(double a0, double a1, double a2, double a3, double a4)
+// Shock flattening (Colella & Woodward 1984, Sec. 4): with the cell's
+// coefficient f < 1 the unlimited interface values move toward the cell
+// average before the limiter (f = 1: untouched, so an unflattened cell
+// computes exactly what it computes without flattening)
+__device__ __forceinline__ Parab ppm_limit_flat(double a2, double aL, double aR, double f)
+{
+    if (f < 1.0) {
+        aL = f * aL + (1.0 - f) * a2;
+        aR = f * aR + (1.0 - f) * a2;
+    }
+    return ppm_limit(a2, aL, aR);
+}
+
+__device__ __forceinline__ Parab ppm(double a0, double a1, double a2, double a3, double a4,
+                                     double f = 1.0)
 {
     double sm = mc_slope(a0, a1, a2);
     double s0 = mc_slope(a1, a2, a3);
     double sp = mc_slope(a2, a3, a4);
-    return ppm_limit(a2, ppm_iface(a1, a2, sm, s0), ppm_iface(a2, a3, s0, sp));
+    return ppm_limit_flat(a2, ppm_iface(a1, a2, sm, s0), ppm_iface(a2, a3, s0, sp), f);
 }
 
 __device__ __forceinline__ Parab ppm_limit(double a2, double aL, double aR)
@@ -217,13 +231,14 @@ __device__ __forceinline__ void trace_parab(const Parab &Pr, const Parab &Pu, co
 __device__ __forceinline__ void trace_cell(const double (&rs)[5], const double (&uns)[5],
                                            const double (&t1s)[5], const double (&t2s)[5],
                                            const double (&ps)[5], double c, double ri, int d,
-                                           double dtdx, Face &hi, Face &lo)
+                                           double dtdx, Face &hi, Face &lo, double f = 1.0)
 {
-    trace_parab(ppm(rs[0], rs[1], rs[2], rs[3], rs[4]),
-                ppm(uns[0], uns[1], uns[2], uns[3], uns[4]),
-                ppm(t1s[0], t1s[1], t1s[2], t1s[3], t1s[4]),
-                ppm(t2s[0], t2s[1], t2s[2], t2s[3], t2s[4]),
-                ppm(ps[0], ps[1], ps[2], ps[3], ps[4]), rs[2], uns[2], c, ri, d, dtdx, hi, lo);
+    trace_parab(ppm(rs[0], rs[1], rs[2], rs[3], rs[4], f),
+                ppm(uns[0], uns[1], uns[2], uns[3], uns[4], f),
+                ppm(t1s[0], t1s[1], t1s[2], t1s[3], t1s[4], f),
+                ppm(t2s[0], t2s[1], t2s[2], t2s[3], t2s[4], f),
+                ppm(ps[0], ps[1], ps[2], ps[3], ps[4], f), rs[2], uns[2], c, ri, d, dtdx, hi,
+                lo);
 }
 
 // PPM along a column marched cell by cell (the z-direction of the marching
@@ -242,12 +257,13 @@ struct PPMColumn {
         s = mc_slope(am1, a0, ap1);
         iL = ppm_iface(am1, a0, sm, s);
     }
-    // the limited parabola of the current cell, given a(k+2); then move to k+1
-    __device__ __forceinline__ Parab step(double ap2)
+    // the limited parabola of the current cell (flattening coefficient f),
+    // given a(k+2); then move to k+1
+    __device__ __forceinline__ Parab step(double ap2, double f = 1.0)
     {
         const double sp = mc_slope(a, an, ap2);
         const double iR = ppm_iface(a, an, s, sp);
-        const Parab P = ppm_limit(a, iL, iR);
+        const Parab P = ppm_limit_flat(a, iL, iR, f);
         a = an;
         an = ap2;
         s = sp;

@@ -37,6 +37,9 @@ __device__ __forceinline__ void stb(const char *pp, unsigned lo, int f0, const F
     ws_st(pp, lo, f0 + 4, f.p);
 }
 
+// FLAT: apply each traced cell's shock-flattening coefficient (computed by
+// k_flatten into the workspace) to its fifteen parabolae
+template <bool FLAT>
 __global__ void __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(3)))
 k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
 {
@@ -148,14 +151,17 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
         const double rho = zr.a, wz = zw.a;
         const double ri = 1.0 / rho;  // as the cell's primitive conversion forms it
         const double c = sound_ri(gamma, zp.a, ri);
+        double fl = 1.0;
+        if (FLAT && inner)
+            fl = o.flat[((long long)(p + 1) * (n1 + 2) + (y + 1)) * (n0 + 2) + (x + 1)];
         Parab Pr, Pu, Pv, Pw, Pp;
         {
             const int slot = (p + 2 + 6) % 3;
-            Pr = zr.step(pl[slot][0][rc]);
-            Pu = zu.step(pl[slot][1][rc]);
-            Pv = zv.step(pl[slot][2][rc]);
-            Pw = zw.step(pl[slot][3][rc]);
-            Pp = zp.step(pl[slot][4][rc]);
+            Pr = zr.step(pl[slot][0][rc], fl);
+            Pu = zu.step(pl[slot][1][rc], fl);
+            Pv = zv.step(pl[slot][2][rc], fl);
+            Pw = zw.step(pl[slot][3][rc], fl);
+            Pp = zp.step(pl[slot][4][rc], fl);
         }
         const int slot = (p + 6) % 3;
         Face hi, lo;
@@ -181,7 +187,7 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
                 a3[m] = pl[slot][3][r];
                 ps[m] = pl[slot][4][r];
             }
-            trace_cell(rs, a1, a2, a3, ps, c, ri, 0, dtdx, hi, lo);
+            trace_cell(rs, a1, a2, a3, ps, c, ri, 0, dtdx, hi, lo, fl);
         }
         if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
         if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }
@@ -201,7 +207,7 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
                 a3[m] = pl[slot][3][r];
                 ps[m] = pl[slot][4][r];
             }
-            trace_cell(rs, a1, a2, a3, ps, c, ri, 1, dtdy, hi, lo);
+            trace_cell(rs, a1, a2, a3, ps, c, ri, 1, dtdy, hi, lo, fl);
         }
         if (gx != 0.0) { hi.u = hi.u + h * gx; lo.u = lo.u + h * gx; }
         if (gy != 0.0) { hi.v = hi.v + h * gy; lo.v = lo.v + h * gy; }

@@ -34,7 +34,8 @@ class HydroBox(C.Structure):
 
 
 class HydroParams(C.Structure):
-    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("grav", C.c_double * 3)]
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("grav", C.c_double * 3),
+                ("flatten", C.c_int32)]
 
 
 class HydroError(RuntimeError):
@@ -105,7 +106,8 @@ def make_box(desc):
 
 
 def make_params(desc):
-    return HydroParams(desc["gamma"], desc["cfl"], (C.c_double * 3)(*desc["grav"]))
+    return HydroParams(desc["gamma"], desc["cfl"], (C.c_double * 3)(*desc["grav"]),
+                       int(desc.get("flatten", 0)))
 
 
 def _stream(stream):

@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts():
     assert C.sizeof(hydro.HydroBox) == 64
-    assert C.sizeof(hydro.HydroParams) == 40
+    assert C.sizeof(hydro.HydroParams) == 48
+    assert hydro.HydroParams.flatten.offset == 40
     assert hydro.HydroBox.dx.offset == 16
     assert hydro.HydroBox.bc_lo.offset == 40
 
@@ -73,7 +74,7 @@ def test_invalid_boxes_rejected(bad):
 
 
 @pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(cfl=0.0), dict(cfl=1.5),
-                                 dict(gamma=float("nan"))])
+                                 dict(gamma=float("nan")), dict(flatten=2), dict(flatten=-1)])
 def test_invalid_params_rejected(bad):
     d = inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1))
     p = inputs.params_desc()
@@ -108,6 +109,13 @@ def test_null_and_overlap_rejected():
     assert L.advance_boxes(1, a, a, None, C.byref(p), a, 1, None, None, ws, nbytes, a,
                            None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_boxes(1, a, None, None) == hydro.HYDRO_EINVAL
+    # flattening reads the fourth ghost layer: a box with three is refused
+    d3 = inputs.box_desc((8, 8, 8), ng=3, bc_lo=(1, 1, 1))
+    b3 = hydro.make_box(d3)
+    pf = hydro.make_params(inputs.params_desc(flatten=1))
+    n3 = hydro.workspace_bytes(d3)
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b3), C.byref(pf), a, None, ws,
+                         n3, a, None) == hydro.HYDRO_EINVAL
 
 
 def test_status_strings():
