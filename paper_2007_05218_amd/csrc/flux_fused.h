@@ -102,11 +102,45 @@ __device__ __forceinline__ Flux fdiff(const Flux &hi, const Flux &lo)
     return d;
 }
 
-// loads at a 32-bit byte offset from a uniform field base (one component of
-// a box is below 2 GiB), so the address is a scalar base plus one VGPR
+// Loads and stores at a 32-bit byte offset from a uniform field base (one
+// component of a box is below 2 GiB), so the address is a scalar base plus
+// one VGPR.  The pointers are marked as global memory: through a generic
+// pointer the access would be a flat one, which the hardware counts with the
+// LDS accesses as well, so every wait for an LDS read would also wait for the
+// loads in flight (the prefetch of the next plane among them).
+typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ double ldb(const double *f, unsigned bo)
 {
-    return *(const double *)((const char *)f + bo);
+    return *(const gdouble *)((const __attribute__((address_space(1))) char *)f + bo);
+}
+__device__ __forceinline__ void stb64(double *f, unsigned bo, double v)
+{
+    *(gdouble *)((__attribute__((address_space(1))) char *)f + bo) = v;
+}
+
+// A plane pointer kept opaque to the compiler (an empty statement that may
+// change it): loads then address as the plane's scalar base plus the lane's
+// 32-bit column offset, instead of a 64-bit per-lane sum hoisted out of the
+// z-loop (two more vector registers held for the whole loop).
+typedef const __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ gchar *opaque_plane(const char *p)
+{
+    asm volatile("" : "+s"(p));
+    return (gchar *)p;
+}
+__device__ __forceinline__ Face load_face_b(gchar *pp, unsigned lo, int f0)
+{
+    auto ld = [&](int f) {
+        return *(const __attribute__((address_space(1))) double *)(pp + lo + f * (kXB * 8));
+    };
+    Face f;
+    f.r = ld(f0 + 0);
+    f.u = ld(f0 + 1);
+    f.v = ld(f0 + 2);
+    f.w = ld(f0 + 3);
+    f.p = ld(f0 + 4);
+    f.ri = 0.0;
+    return f;
 }
 
 // a traced state from fields f0 .. f0+4 of the column at offset lo of plane pp
@@ -296,7 +330,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
     double dtn = __longlong_as_double((long long)kInfBits);
 
     for (int q = T.z0 - 1; q <= T.z1; ++q) {
-        const char *pq = ws.plane(q);
+        gchar *pq = opaque_plane(ws.plane(q));
         // (the (s|z) corner states of the warm-up plane use the round-1 z-flux
         // below it, which this segment does not have: the previous segment
         // covers them)
@@ -309,7 +343,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         const Face qx_lo = load_face_b(pq, wo, QLO(0, 0)), qx_hi = load_face_b(pq, wo, QHI(0, 0));
         const Face qy_lo = load_face_b(pq, wo, QLO(1, 0));
         const Face qz_lo = load_face_b(pq, wo, QLO(2, 0)), qz_hi = load_face_b(pq, wo, QHI(2, 0));
-        const Face qz_lo_n = load_face_b(ws.plane(q + 1), wo, QLO(2, 0));  // next plane
+        const Face qz_lo_n = load_face_b(opaque_plane(ws.plane(q + 1)), wo, QLO(2, 0));  // next plane
         __syncthreads();
         // ---------------------------------------------------- round-1 fluxes
         // through each lane's low x/y faces (the low neighbour's high state
@@ -398,7 +432,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         const int p = q - 1;
         const bool pv = p >= T.z0;  // plane p is finished in this segment
         const bool rp_c = inr(p, 0, n2 - 1);
-        const char *pp = ws.plane(p);
+        gchar *pp = opaque_plane(ws.plane(p));
         Face xl, xh, yl, yh;
         // (lanes whose final x or y states are never used skip reading
         // their traced states: the ring rows for x, the ring columns for y,
@@ -482,7 +516,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 if (!isfinite(Us[v])) err |= HYDRO_ERR_NONFINITE;
-                *(double *)((char *)(o.Un + v * g.cs) + bo) = Us[v];
+                stb64(o.Un + v * g.cs, bo, Us[v]);
             }
             if (Us[0] <= 0.0) err |= HYDRO_ERR_RHO;
             if (qn.p <= 0.0) err |= HYDRO_ERR_P;
