@@ -10,9 +10,9 @@
 // else chi = 0.  The axis coefficient is 1 - max(chi[i], chi[i+s]) with s
 // toward the lower-pressure neighbour (the cell just behind a shock is
 // flattened with it), and the cell's coefficient is the smallest of its three
-// axes'.  One thread per traced cell (x in [-1,n0], y in [-1,n1],
-// z in [-1,n2]); the 7-cell pencils reach four cells out, into the fourth
-// ghost layer.
+// axes' (x, then y, then z).  Computed for every traced cell (x in [-1,n0],
+// y in [-1,n1], z in [-1,n2]); the 7-cell pencils reach four cells out, into
+// the fourth ghost layer.
 #pragma once
 
 namespace {
@@ -37,35 +37,85 @@ __device__ __forceinline__ double flat_axis(const double (&p)[7], const double (
     return 1.0 - dmax(chi[1], nb);
 }
 
+// Tiles: a 256-thread block covers kFlB x kFlB columns of the traced region
+// and marches over a z-segment of at most kFlZ planes.  Each plane's
+// pressures and in-plane velocities, on the tile plus a three-cell ring, are
+// converted from U once into LDS (the x and y pencils read them there); each
+// column carries its own z-pencil (pressure and normal velocity of the
+// planes z-3 .. z+3) in registers, converting one new plane ahead per step.
+constexpr int kFlW = kFlB + 6;
+
 __global__ void __launch_bounds__(kBlock) k_flatten(Launch L, double gamma)
 {
+    __shared__ double sp[kFlW * kFlW], su[kFlW * kFlW], sv[kFlW * kFlW];
     Box1 o = resolve(L);
     const Geo &g = o.g;
-    const long long ex0 = g.n[0] + 2, ex1 = g.n[1] + 2, ex2 = g.n[2] + 2;
-    const long long t = o.blk * kBlock + threadIdx.x;
-    if (t >= ex0 * ex1 * ex2) return;
-    const int x = (int)(t % ex0) - 1;
-    const int y = (int)((t / ex0) % ex1) - 1;
-    const int z = (int)(t / (ex0 * ex1)) - 1;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], ng = g.ng;
+    const int ntx = (n0 + 2 + kFlB - 1) / kFlB, nty = (n1 + 2 + kFlB - 1) / kFlB;
+    long long tt = o.blk;
+    const int ix = (int)(tt % ntx);
+    tt /= ntx;
+    const int iy = (int)(tt % nty);
+    const int iz = (int)(tt / nty);
+    const int x0 = -1 + ix * kFlB, y0 = -1 + iy * kFlB;
+    const int z0 = -1 + iz * kFlZ, z1 = min(n2 + 1, z0 + kFlZ);
+    const int t = threadIdx.x, tx = t % kFlB, ty = t / kFlB;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool inner = x <= n0 && y <= n1;
     const double gm1 = gamma - 1.0;
     const double *U = o.U;
-    const long long c0 = cell(g, x, y, z);
-    double f = 1.0;
+    // primitives of a cell, its coordinates clamped into the ghosted box
+    // (clamped cells only feed lanes whose results are not stored)
+    auto prim_at = [&](int i, int j, int k) {
+        i = min(max(i, -ng), n0 + ng - 1);
+        j = min(max(j, -ng), n1 + ng - 1);
+        k = min(max(k, -ng), n2 + ng - 1);
+        const long long c = cell(g, i, j, k);
+        return prim_of(U[c], U[g.cs + c], U[2 * g.cs + c], U[3 * g.cs + c], U[4 * g.cs + c], gm1);
+    };
+    // own column's z-pencil: pressure and z-velocity of planes z-3 .. z+3
+    double zp[7], zw[7];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const long long st = stride(g, d);
-        double p[7], u[7];
+    for (int m = 0; m < 6; ++m) {
+        const Prim q = prim_at(x, y, z0 - 3 + m);
+        zp[m] = q.p;
+        zw[m] = q.w;
+    }
+    for (int z = z0; z < z1; ++z) {
+        {
+            const Prim q = prim_at(x, y, z + 3);
+            zp[6] = q.p;
+            zw[6] = q.w;
+        }
+        for (int r = t; r < kFlW * kFlW; r += kBlock) {
+            const Prim q = prim_at(x0 - 3 + r % kFlW, y0 - 3 + r / kFlW, z);
+            sp[r] = q.p;
+            su[r] = q.u;
+            sv[r] = q.v;
+        }
+        __syncthreads();
+        const int rc = (ty + 3) * kFlW + (tx + 3);
+        double px[7], ux[7], py[7], vy[7];
 #pragma unroll
         for (int m = 0; m < 7; ++m) {
-            const long long c = c0 + (m - 3) * st;
-            const Prim q = prim_of(U[c], U[g.cs + c], U[2 * g.cs + c], U[3 * g.cs + c],
-                                   U[4 * g.cs + c], gm1);
-            p[m] = q.p;
-            u[m] = d == 0 ? q.u : (d == 1 ? q.v : q.w);
+            px[m] = sp[rc + (m - 3)];
+            ux[m] = su[rc + (m - 3)];
+            py[m] = sp[rc + (m - 3) * kFlW];
+            vy[m] = sv[rc + (m - 3) * kFlW];
         }
-        f = dmin(f, flat_axis(p, u));
+        double f = 1.0;
+        f = dmin(f, flat_axis(px, ux));
+        f = dmin(f, flat_axis(py, vy));
+        f = dmin(f, flat_axis(zp, zw));
+        if (inner)
+            o.flat[((long long)(z + 1) * (n1 + 2) + (y + 1)) * (n0 + 2) + (x + 1)] = f;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            zp[m] = zp[m + 1];
+            zw[m] = zw[m + 1];
+        }
+        __syncthreads();
     }
-    o.flat[t] = f;
 }
 
 }  // namespace

@@ -146,6 +146,10 @@ __device__ __forceinline__ bool reg_cell(const Reg &r, long long t, int &i, int 
     return true;
 }
 
+// tiles of the flattening kernel (flatten.h): kFlB x kFlB columns of the
+// traced region, z-segments of kFlZ planes
+constexpr int kFlB = 16, kFlZ = 32;
+
 // blocks of one box in a stage
 __host__ inline long long stage_blocks(const Geo &g, int st)
 {
@@ -160,8 +164,9 @@ __host__ inline long long stage_blocks(const Geo &g, int st)
                ((g.n[2] + g.tzs2 - 1) / g.tzs2);
     }
     const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
-    if (st == ST_FLAT)  // one thread per traced cell
-        return ((long long)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2) + kBlock - 1) / kBlock;
+    if (st == ST_FLAT)
+        return (long long)((g.n[0] + 2 + kFlB - 1) / kFlB) * ((g.n[1] + 2 + kFlB - 1) / kFlB) *
+               ((g.n[2] + 2 + kFlZ - 1) / kFlZ);
     long long items = st == ST_FILL ? g.cs - nv : nv;
     if (st == ST_DT) {
         long long b = (items + (long long)kBlock * kDtCellsPerThread - 1) /
