@@ -44,7 +44,7 @@ HBM_PEAK = 8.0e12
 KERNEL_STAGES = {"trace": ["prim", "trace"],
                  "flux_update": ["flux1", "corner_flux2", "final_flux3", "update"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rt512_traffic.json")
-KERNEL_SYMBOL = {"trace": "k_trace_fused", "flux_update": "k_flux_fused"}
+KERNEL_SYMBOL = {"trace": "k_trace_fused<false>", "flux_update": "k_flux_fused"}
 
 
 # the sources the profiled step kernels are built from
