@@ -123,7 +123,11 @@ __device__ __forceinline__ double ws_ld(const char *pp, unsigned lo, int f)
 }
 __device__ __forceinline__ void ws_st(const char *pp, unsigned lo, int f, double v)
 {
-    *(double *)((const_cast<char *>(pp) + (size_t)lo) + f * (kXB * 8)) = v;
+    // (streamed past the caches: the workspace is far larger than them and
+    // is read back by the next kernel, not this one)
+    __builtin_nontemporal_store(
+        v, (__attribute__((address_space(1))) double *)((const_cast<char *>(pp) + (size_t)lo) +
+                                                        f * (kXB * 8)));
 }
 
 struct Reg {
