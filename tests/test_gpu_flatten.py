@@ -137,3 +137,54 @@ def test_flattened_sedov_follows_similarity(gpu):
     assert int(B.err.item()) & 7 == 0
     R = sedov_exact.measured_radius(inputs.valid(B.state(), box)[0], r, n, 0.5)
     assert R == pytest.approx(sedov_exact.shock_radius(t), rel=0.04)
+
+
+@pytest.mark.parametrize("flatten", [0, 1])
+def test_full_size_sedov_level_sampled(gpu, orc, flatten):
+    # the benchmark's Sedov configuration (256^3 as 64 boxes of 64^3, with and
+    # without flattening): the tenth step, from the state the GPU reached in
+    # nine (the blast has started and flattening acts), against the oracle's
+    # 256^3 box on sampled regions, several of them straddling box boundaries
+    import torch
+    n, bs = 256, 64
+    states, boxes, prm, lo, til = inputs.sedov_level(n, bs)
+    prm = dict(prm, flatten=flatten)
+    print("sedov level 256 flatten", flatten, flush=True)
+    tiling = gpu.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    lev = gpu.Level(states, boxes, prm, shared_dt=True, tiling=tiling)
+
+    def domain():
+        D = np.zeros((5, n, n, n))
+        for G, b, l in zip(lev.states(), boxes, lo):
+            m = b["n"]
+            D[:, l[2]:l[2] + m[2], l[1]:l[1] + m[1], l[0]:l[0] + m[0]] = inputs.valid(G, b)
+        return D
+
+    lev.run(9)
+    torch.cuda.synchronize()
+    U, box, _ = inputs.sedov(n)
+    inputs.valid(U, box)[...] = domain()
+    lev.step()
+    torch.cuda.synchronize()
+    gdt = lev.dt_min.item()
+    D = domain()
+    del lev
+    tiling.close()
+    torch.cuda.empty_cache()
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    orc.fill_ghosts(U, ob)
+    odt = orc.estimate_dt(U, ob, op)
+    assert gdt == odt
+    ng = box["ng"]
+    Unew = np.empty_like(U)
+    regions = [((124, 124, 124), (132, 132, 132)),   # the blast, across 8 boxes
+               ((60, 120, 126), (68, 128, 130)),     # a box face in x
+               ((0, 0, 0), (4, 4, 4)), ((252, 252, 252), (256, 256, 256)),
+               ((126, 62, 60), (130, 66, 68))]       # box faces in y and z
+    for rlo, rhi in regions:
+        orc.advance_region(U, Unew, ob, op, odt, rlo, rhi)
+        o = Unew[:, ng + rlo[2]:ng + rhi[2], ng + rlo[1]:ng + rhi[1], ng + rlo[0]:ng + rhi[0]]
+        g = D[:, rlo[2]:rhi[2], rlo[1]:rhi[1], rlo[0]:rhi[0]]
+        err, bw = compare(g, o)
+        print("region", rlo, rhi, err, bw, flush=True)
+        assert err <= TOL and bw == 1.0
