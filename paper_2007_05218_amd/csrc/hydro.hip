@@ -34,6 +34,7 @@
 #include <string.h>
 
 #include <new>
+#include <algorithm>
 #include <vector>
 
 using namespace hydro;
@@ -200,6 +201,7 @@ struct Launch {
     const long long *wsoff;  // doubles from the workspace base
     const double *dts;
     int dt_stride;
+    const int *order;  // box of each work-list position (null: the identity)
     // optional: the CFL timestep of the new state, reduced by the flux kernel
     // (per box, as 64-bit patterns for atomicMin) and the minimum over boxes
     unsigned long long *dtn;
@@ -240,12 +242,13 @@ __device__ __forceinline__ Box1 resolve(const Launch &L)
             if (L.pre[mid] <= x) lo = mid;
             else hi = mid;
         }
-        o.b = lo;
-        o.g = L.geos[lo];
-        o.U = L.Us ? L.Us[lo] : nullptr;
-        o.Un = L.Uns ? L.Uns[lo] : nullptr;
-        o.ws.base = L.ws ? (char *)(L.ws + L.wsoff[lo]) : nullptr;
-        o.dt = L.dts ? L.dts + (long long)lo * L.dt_stride : nullptr;
+        const int b = L.order ? L.order[lo] : lo;
+        o.b = b;
+        o.g = L.geos[b];
+        o.U = L.Us ? L.Us[b] : nullptr;
+        o.Un = L.Uns ? L.Uns[b] : nullptr;
+        o.ws.base = L.ws ? (char *)(L.ws + L.wsoff[b]) : nullptr;
+        o.dt = L.dts ? L.dts + (long long)b * L.dt_stride : nullptr;
         o.blk = x - L.pre[lo];
         o.nblk = L.pre[lo + 1] - L.pre[lo];
     }
@@ -519,12 +522,16 @@ hydro_status launch_status()
 
 // the whole advance, given a launch template and per-stage grid sizes
 hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *const *pre,
-                             const hydro_params *prm, int32_t *err32, hipStream_t st)
+                             const int *const *order, const hydro_params *prm, int32_t *err32,
+                             hipStream_t st)
 {
     int *err_dev = (int *)err32;
     const double gamma = prm->gamma;
     auto set = [&](int stage) {
-        if (L.nb) L.pre = pre[stage];
+        if (L.nb) {
+            L.pre = pre[stage];
+            L.order = order[stage];
+        }
         return dim3((unsigned)grid[stage]);
     };
     prof(PG_TRACE, 0, st);
@@ -630,9 +637,12 @@ struct Plan {
     std::vector<Geo> geos;
     size_t ws_bytes;
     long long grid[ST_COUNT];  // total blocks per stage
-    void *dev;                 // [Geo nb][long long wsoff nb][unsigned pre ST_COUNT x (nb+1)]
+    // device buffer: [Geo nb][long long wsoff nb][int order ST_COUNT x nb]
+    // [unsigned pre ST_COUNT x (nb+1)]
+    void *dev;
     const Geo *geos_dev;
     const long long *wsoff_dev;
+    const int *order_dev[ST_COUNT];
     const unsigned *pre_dev[ST_COUNT];
 };
 
@@ -717,7 +727,7 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
     for (int s = 0; s < ST_COUNT; ++s) grid[s] = stage_blocks(g, s);
     Launch L = single(g, U_dev, U_new_dev, ws_dev, dt_dev);
     L.dtn = (unsigned long long *)dt_next_dev;
-    return enqueue_advance(L, grid, nullptr, prm, err_dev, (hipStream_t)stream);
+    return enqueue_advance(L, grid, nullptr, nullptr, prm, err_dev, (hipStream_t)stream);
 }
 
 hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,
@@ -755,11 +765,27 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
         wsoff[b] = (long long)(P->ws_bytes / sizeof(double));
         P->ws_bytes += box_ws_bytes(g);
     }
+    // Work lists: for the marching kernels, boxes in order of decreasing
+    // block length (the z-planes one block marches over), so the longest
+    // blocks start first and short ones fill the end of the launch; the
+    // other stages take the boxes in the given order.
+    std::vector<int> order((size_t)ST_COUNT * nb);
+    for (int s = 0; s < ST_COUNT; ++s) {
+        int *o = &order[(size_t)s * nb];
+        for (int b = 0; b < nb; ++b) o[b] = b;
+        auto zlen = [&](int b) {
+            const Geo &g = P->geos[b];
+            if (s == ST_FLUX) return g.tzs2 < g.n[2] ? g.tzs2 : g.n[2];
+            if (s == ST_TRACE) return g.tzs1 < g.n[2] + 2 ? g.tzs1 : g.n[2] + 2;
+            return 0;
+        };
+        std::stable_sort(o, o + nb, [&](int a, int b) { return zlen(a) > zlen(b); });
+    }
     for (int s = 0; s < ST_COUNT; ++s) {
         unsigned long long acc = 0;
-        for (int b = 0; b < nb; ++b) {
-            pre[(size_t)s * (nb + 1) + b] = (unsigned)acc;
-            acc += (unsigned long long)stage_blocks(P->geos[b], s);
+        for (int i = 0; i < nb; ++i) {
+            pre[(size_t)s * (nb + 1) + i] = (unsigned)acc;
+            acc += (unsigned long long)stage_blocks(P->geos[order[(size_t)s * nb + i]], s);
         }
         if (acc >= (1ULL << 31)) {
             delete P;
@@ -769,8 +795,9 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
         P->grid[s] = (long long)acc;
     }
     size_t szg = sizeof(Geo) * nb, szw = sizeof(long long) * nb,
-           szp = sizeof(unsigned) * pre.size();
-    size_t offw = (szg + 255) / 256 * 256, offp = offw + (szw + 255) / 256 * 256;
+           szo = sizeof(int) * order.size(), szp = sizeof(unsigned) * pre.size();
+    size_t offw = (szg + 255) / 256 * 256, offo = offw + (szw + 255) / 256 * 256,
+           offp = offo + (szo + 255) / 256 * 256;
     if (hipMalloc(&P->dev, offp + szp) != hipSuccess) {
         delete P;
         return HYDRO_EHIP;
@@ -778,6 +805,7 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
     char *base = (char *)P->dev;
     if (hipMemcpy(base, P->geos.data(), szg, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + offw, wsoff.data(), szw, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + offo, order.data(), szo, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + offp, pre.data(), szp, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(P->dev);
         delete P;
@@ -785,6 +813,8 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
     }
     P->geos_dev = (const Geo *)base;
     P->wsoff_dev = (const long long *)(base + offw);
+    for (int s = 0; s < ST_COUNT; ++s)
+        P->order_dev[s] = (const int *)(base + offo) + (size_t)s * nb;
     for (int s = 0; s < ST_COUNT; ++s)
         P->pre_dev[s] = (const unsigned *)(base + offp) + (size_t)s * (nb + 1);
     *plan_out = P;
@@ -825,11 +855,13 @@ hydro_status estimate_dt_boxes(int nb, double *const *U_ptrs_dev, const void *pl
     hipStream_t st = (hipStream_t)stream;
     Launch L = batch_launch(P, U_ptrs_dev, nullptr, nullptr, nullptr, 0);
     L.pre = P->pre_dev[ST_FILL];
+    L.order = P->order_dev[ST_FILL];
     prof(PG_FILL, 0, st);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)P->grid[ST_FILL]), dim3(kBlock), 0, st, L,
                        (unsigned long long *)dt_dev, (unsigned long long *)dt_min_dev);
     prof(PG_FILL, 1, st);
     L.pre = P->pre_dev[ST_DT];
+    L.order = P->order_dev[ST_DT];
     prof(PG_DT, 0, st);
     hipLaunchKernelGGL(k_dt, dim3((unsigned)P->grid[ST_DT]), dim3(kBlock), 0, st, L,
                        prm->gamma, prm->cfl, (unsigned long long *)dt_dev,
@@ -863,7 +895,8 @@ hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
                             dt_stride);
     L.dtn = (unsigned long long *)dt_next_dev;
     L.dtn_min = (unsigned long long *)dt_next_min_dev;
-    return enqueue_advance(L, P->grid, P->pre_dev, prm, err_dev, (hipStream_t)stream);
+    return enqueue_advance(L, P->grid, P->pre_dev, P->order_dev, prm, err_dev,
+                           (hipStream_t)stream);
 }
 
 hydro_status hydro_fill_ghosts_boxes(int nb, double *const *U_ptrs_dev, const void *plan,
@@ -874,6 +907,7 @@ hydro_status hydro_fill_ghosts_boxes(int nb, double *const *U_ptrs_dev, const vo
     hipStream_t st = (hipStream_t)stream;
     Launch L = batch_launch(P, U_ptrs_dev, nullptr, nullptr, nullptr, 0);
     L.pre = P->pre_dev[ST_FILL];
+    L.order = P->order_dev[ST_FILL];
     prof(PG_FILL, 0, st);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)P->grid[ST_FILL]), dim3(kBlock), 0, st, L,
                        (unsigned long long *)nullptr, (unsigned long long *)nullptr);
