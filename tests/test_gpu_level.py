@@ -60,6 +60,34 @@ def test_level_fill_matches_oracle(gpu, lay):
     til_h.close()
 
 
+def test_level_fill_mixed_ghost_depths(gpu):
+    # boxes of one level may carry different ghost depths (3 and 4 here)
+    import torch
+    dom = (24, 20, 16)
+    box = inputs.box_desc(dom, 4, bc_lo=(P, R, O), bc_hi=(P, O, R))
+    rng = np.random.default_rng(21)
+    U = np.zeros(inputs.state_shape(box))
+    inputs.valid(U, box)[...] = rng.standard_normal(inputs.valid(U, box).shape)
+    states, boxes, lo, til = inputs.tile(U, box, ([0, 10, 24], [0, 20], [0, 7, 16]))
+    for i in (1, 2):  # re-cut two boxes with three ghost layers
+        b = dict(boxes[i], ng=3)
+        W = np.zeros(inputs.state_shape(b))
+        inputs.valid(W, b)[...] = inputs.valid(states[i], boxes[i])
+        states[i], boxes[i] = W, b
+    want = olev.fill_ghosts_level(states, boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    dev = []
+    for S, b in zip(states, boxes):
+        T = np.full_like(S, np.nan)
+        inputs.valid(T, b)[...] = inputs.valid(S, b)
+        dev.append(torch.as_tensor(T).cuda())
+    tl = gpu.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    gpu.fill_ghosts_level(tl, gpu.pointer_array(dev))
+    torch.cuda.synchronize()
+    for G, W in zip(dev, want):
+        assert np.array_equal(G.cpu().numpy(), W)
+    tl.close()
+
+
 def _domain_run(gpu, U, box, prm, steps):
     import torch
     B = gpu.Box(U, box, prm)
