@@ -7,8 +7,9 @@
 // from them.  Output: the new state of the tile's cells (and, optionally,
 // the CFL timestep of the new state).  Nothing else goes back to HBM:
 // x-neighbour exchanges stay inside the wavefront (DPP lane shifts),
-// y-neighbour exchanges go through LDS, and the z-direction couplings (fluxes through z-faces and the z-differences of
-// the (z|s) fluxes) are carried from plane to plane in registers or, for
+// y-neighbour exchanges go through LDS, and the z-direction couplings
+// (fluxes through z-faces and the z-differences of the (z|s) fluxes) are
+// carried from plane to plane in registers or, for
 // values a lane alone needs a plane later, in its own LDS slots (which keeps
 // the kernel within its register budget: spilled registers would go to
 // scratch memory and cost HBM traffic).

@@ -1,29 +1,32 @@
 // hydro.hip -- gfx950 kernels and the C ABI (include/hydro.h) of one
 // CTU-PPM-HLLC hydro step on boxes with ghost cells.
 //
-// Stage pipeline (one launch per stage and direction, covering one box or a
-// whole batch of boxes; intermediates live in the caller's HBM workspace,
-// one dense ghosted array per field, x fastest, so every access is a
-// coalesced unit-stride stream along x):
-//   fill    ghost cells of U from the boundary kinds (one pass: each axis
-//           maps independently, so edges and corners need no ordering)
-//   dt      per-cell min_d dx_d/(|u_d|+c), wave64 shuffle -> LDS -> one
-//           64-bit atomicMin per block on the bit pattern (positive doubles
-//           order like unsigned integers), scaled by cfl
-//   prim    rho,u,v,w,p,c on every cell of the ghosted box
-//   trace   PPM + characteristic tracing, both faces, each direction, on the
-//           cells one beyond the valid region, + half-step gravity kick
-//   flux1   HLLC on the traced states at every face the corner step reads
-//   flux2   corner coupling (dt/3 transverse corrections) + HLLC: six
-//           (normal | transverse) flux families
-//   flux3   final states (dt/2 corrections by both round-2 transverse flux
-//           differences) + HLLC
-//   update  conservative update + time-centred gravity source + error bits
+// The step's stages (the method's A0-A8) run in a few fused launches, each
+// covering one box or a whole batch of boxes:
+//   k_fill         ghost cells of U from the boundary kinds (one pass: each
+//                  axis maps independently, so edges and corners need no
+//                  ordering)
+//   k_dt           per-cell min_d dx_d/(|u_d|+c), wave64 shuffle -> LDS -> one
+//                  64-bit atomicMin per block on the bit pattern (positive
+//                  doubles order like unsigned integers), scaled by cfl; only
+//                  for a state no advance produced
+//   k_flatten      shock-flattening coefficients (flatten.h; only with
+//                  flattening on)
+//   k_trace_fused  primitives, PPM and characteristic tracing, both faces,
+//                  each direction, on the cells one beyond the valid region,
+//                  + half-step gravity kick (trace_fused.h); the traced
+//                  states go to the caller's HBM workspace
+//   k_flux_fused   round-1 HLLC, corner coupling (dt/3 transverse
+//                  corrections) + round-2 HLLC, final states (dt/2) +
+//                  round-3 HLLC, conservative update + time-centred gravity
+//                  source + error bits, and the new state's CFL timestep
+//                  (flux_fused.h)
 //
-// Batching: a plan lists, for every stage, the prefix sum of each box's
-// block count; a block finds its box by binary search, so one launch per
-// stage serves hundreds of uneven boxes (the per-box launches of the
-// paper's Sec. IV-A replaced by one launch over the whole list).
+// Batching: a plan lists, for every stage, a work list of the boxes and the
+// prefix sum of their block counts; a block finds its box by binary search,
+// so one launch per stage serves hundreds of uneven boxes (the per-box
+// launches of the paper's Sec. IV-A replaced by one launch over the whole
+// list).
 #include "hydro_common.h"
 #include "../../include/hydro.h"
 

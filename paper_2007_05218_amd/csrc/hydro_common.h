@@ -3,7 +3,8 @@
 // Scheme: the paper's Castro hydro (bibliography entry CastroI; Sec. III
 // describes its slope stencil and polynomial reconstruction): PPM parabolae
 // with the monotonised-central slope and the Colella-Woodward (1984)
-// parabola limiter, characteristic tracing to the faces, an HLLC Riemann
+// parabola limiter (optionally after their shock flattening), characteristic
+// tracing to the faces, an HLLC Riemann
 // solver (Toro, Spruce & Speares 1994) with Davis (1988) wave-speed bounds,
 // and the 3-D corner transport upwind coupling (Colella 1990, Saltzman 1994).
 //
