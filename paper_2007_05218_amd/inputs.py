@@ -145,10 +145,12 @@ def _modes(rng, n, L, xyz):
                 break
         a = rng.uniform(0.5, 1.0)
         ph = rng.uniform(0.0, 2 * np.pi)
-        arg = sum(2 * np.pi * k[d] * xyz[d] / L[d] for d in range(3))
-        S = S + a * np.cos(arg + ph)
+        # a cos(k.x + ph) as the real part of a product of one-dimensional
+        # complex exponentials (one multiply per cell instead of a cosine)
+        e = [np.exp(1j * (2 * np.pi * k[d] / L[d]) * xyz[d]) for d in range(3)]
+        S = S + (a * np.exp(1j * ph)) * (e[2] * e[1]) * e[0]
         asum += a
-    return S / asum
+    return np.real(S) / asum
 
 
 def smooth(n, seed, dx=None, ng=NG):

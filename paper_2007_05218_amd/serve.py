@@ -1,7 +1,8 @@
 """Continuous-batching server for independent hydro runs on one GPU.
 
-Each request is a whole hydro run: a cubic box, an initial-condition family
-and seed, and a number of steps.  The server admits arriving requests while
+Each request is a whole hydro run: a cubic box, its initial state (supplied
+with the request, or built from an initial-condition family and seed), and
+a number of steps.  The server admits arriving requests while
 the HBM ledger (state ping-pong buffers plus the request's share of the
 batch workspace) stays within the budget and a slot is free, keeps every
 admitted state resident on the device, and advances all active requests
@@ -27,7 +28,7 @@ import time
 
 class Request:
     __slots__ = ("id", "arrival", "n", "steps", "family", "seed", "remaining", "need",
-                 "t_admit", "t_done", "done_token", "handle", "result", "cells")
+                 "t_admit", "t_done", "done_token", "handle", "result", "cells", "payload")
 
     def __init__(self, spec):
         self.id = spec["id"]
@@ -44,6 +45,9 @@ class Request:
         self.done_token = None
         self.handle = None
         self.result = None
+        # the client's initial state (host state array, box, params), if it
+        # came with the request
+        self.payload = spec.get("state")
 
 
 class GpuExecutor:
@@ -73,8 +77,12 @@ class GpuExecutor:
     # -- membership
     def admit(self, req):
         torch = self.torch
-        U, box, prm = self.inputs.request_state({"family": req.family, "n": req.n,
-                                                 "seed": req.seed})
+        if req.payload is not None:
+            U, box, prm = req.payload
+            req.payload = None  # uploaded: the host copy is no longer held
+        else:
+            U, box, prm = self.inputs.request_state({"family": req.family, "n": req.n,
+                                                     "seed": req.seed})
         if self.prm is None:
             self.prm = prm
         Ud = torch.as_tensor(U).to(self.device, non_blocking=False)

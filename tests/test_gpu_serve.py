@@ -43,6 +43,13 @@ def test_served_equals_alone(gpu, orc):
     assert err <= 1e-11 and bw == 1.0
     m = srv.metrics()
     assert m["p50_s"] > 0 and m["p99_s"] >= m["p50_s"]
+    # requests that bring their initial states give the same results
+    for s in specs:
+        s["state"] = inputs.request_state(s)
+    ex2 = GpuExecutor(keep_results=True)
+    done2 = Server(ex2, budget_bytes=20e9, max_active=6).run(specs)
+    for a, b in zip(done, done2):
+        assert np.array_equal(a.result, b.result), a.id
 
 
 def test_graph_replay_equals_eager(gpu):
