@@ -66,6 +66,7 @@ class GpuExecutor:
         self.stream = torch.cuda.current_stream()
         self.active = []
         self.plan = None
+        self.retired = []  # plans of earlier batches, freed once the device is idle
         self.prm = None
         self.err = torch.zeros(1, dtype=torch.int32, device=device)
 
@@ -97,7 +98,9 @@ class GpuExecutor:
         torch = self.torch
         self.active = list(reqs)
         if self.plan is not None:
-            self.plan.close()
+            # (freeing device memory waits for all queued work: the plan is
+            # kept until the loop has drained the device)
+            self.retired.append(self.plan)
             self.plan = None
         if not reqs:
             return
@@ -141,6 +144,12 @@ class GpuExecutor:
 
     def error_bits(self):
         return int(self.err.item())
+
+    def drained(self):
+        """The device has finished all queued work: free retired plans."""
+        for p in self.retired:
+            p.close()
+        self.retired = []
 
 
 class Server:
@@ -188,7 +197,11 @@ class Server:
                 changed = True
             self.peak_ledger = max(self.peak_ledger, self.ledger)
             if not active:
-                # idle until the next arrival
+                # idle until the next arrival (the device drains meanwhile)
+                while inflight:
+                    self.ex.wait(inflight.popleft())
+                if hasattr(self.ex, "drained"):
+                    self.ex.drained()
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
                     self.sleep(wait)
@@ -217,6 +230,8 @@ class Server:
                 self.ex.wait(inflight.popleft())
         while inflight:
             self.ex.wait(inflight.popleft())
+        if hasattr(self.ex, "drained"):
+            self.ex.drained()
         for r in done:
             r.t_done = self.ex.elapsed(t0_tok, r.done_token)
         self.requests = sorted(done, key=lambda r: r.id)
