@@ -234,3 +234,34 @@ def test_tiled_flattened_level_graph_replay(gpu):
         for a, b, box in zip([u.cpu().numpy() for u in lev.U], refs[rep], boxes):
             assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box)), rep
     assert int(lev.err.item()) & 7 == 0
+
+
+def test_sedov_shock_radius_converges(gpu):
+    # the blast front converges to the self-similar radius as the grid is
+    # refined (64^3, 128^3, 256^3, each as boxes of 64^3 tiling the domain)
+    import torch
+    errs = []
+    for n in (64, 128, 256):
+        states, boxes, prm, lo, til = inputs.sedov_level(n, 64)
+        tiling = gpu.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+        lev = gpu.Level(states, boxes, prm, shared_dt=True, tiling=tiling)
+        t = 0.0
+        while t < 0.03:
+            lev.step()
+            t += lev.dt_min.item()
+        torch.cuda.synchronize()
+        assert int(lev.err.item()) & 7 == 0
+        D = np.zeros((n, n, n))
+        for G, b, l in zip(lev.states(), boxes, lo):
+            m = b["n"]
+            D[l[2]:l[2] + m[2], l[1]:l[1] + m[1], l[0]:l[0] + m[0]] = inputs.valid(G, b)[0]
+        x = (np.arange(n) + 0.5) / n
+        r = np.sqrt((x[None, None, :] - 0.5) ** 2 + (x[None, :, None] - 0.5) ** 2 +
+                    (x[:, None, None] - 0.5) ** 2)
+        R = sedov_exact.measured_radius(D, r, n, 0.5)
+        errs.append(abs(R / sedov_exact.shock_radius(t) - 1.0))
+        print("sedov n=%d t=%.4f R=%.4f err=%.4f" % (n, t, R, errs[-1]), flush=True)
+        del lev
+        tiling.close()
+        torch.cuda.empty_cache()
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.015, errs
