@@ -152,6 +152,32 @@ def time_level(hydro, torch, inputs, steps, warmup):
     js = autotune.table_json(table) if table else None
     ms_default = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup)
     ms_batched = _time_level_once(hydro, torch, states, boxes, prm, steps, warmup, js)
+    # the batched step captured in a HIP graph (two steps per graph, so the
+    # states end in the buffers they started in), replayed
+    lev = hydro.Level(states, boxes, prm, shared_dt=True, autotune_json=js)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        lev.step()
+        lev.step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        lev.step()
+        lev.step()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, steps // 2)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / (2 * reps)
+    del graph, lev
+    torch.cuda.empty_cache()
     # the same boxes, one library call per box and stage (one stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     Us = [torch.tensor(u, device="cuda") for u in states]
@@ -223,6 +249,7 @@ def time_level(hydro, torch, inputs, steps, warmup):
             "per_box_cu_per_s": cells * steps / (ms_per_box * 1e-3),
             "per_box_8_streams_cu_per_s": cells * steps / (ms_streams * 1e-3),
             "batched_ms_per_step": ms_batched / steps, "per_box_ms_per_step": ms_per_box / steps,
+            "batched_graph_ms_per_step": ms_graph,
             "autotune_s": tune_s, "tile_table": table}
 
 
