@@ -265,3 +265,19 @@ def test_sedov_shock_radius_converges(gpu):
         tiling.close()
         torch.cuda.empty_cache()
     assert errs[0] > errs[1] > errs[2] and errs[2] < 0.015, errs
+
+
+def test_level_fill_rejects_a_mismatched_pointer_count(gpu):
+    # argument errors are returned before anything is launched
+    import ctypes
+    import torch
+    U, box, prm = inputs.sedov(32)
+    states, boxes, lo, til = inputs.tile(U, box, ([0, 16, 32], [0, 32], [0, 32]))
+    tl = gpu.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    dev = [torch.as_tensor(st).cuda() for st in states]
+    ptrs = gpu.pointer_array(dev)
+    L = gpu.lib()
+    assert L.hydro_fill_ghosts_level(1, ctypes.c_void_p(ptrs.data_ptr()), tl.handle,
+                                     None) == gpu.HYDRO_EINVAL
+    assert L.hydro_fill_ghosts_level(2, None, tl.handle, None) == gpu.HYDRO_EINVAL
+    tl.close()
