@@ -20,7 +20,9 @@
  *      transverse flux difference, then HLLC (round 2, 6 flux families),
  *   A7 final states: each traced state corrected by dt/2 of the two
  *      round-2 transverse flux differences, then HLLC (round 3),
- *   A8 conservative update plus a time-centred constant-gravity source.
+ *   A8 conservative update plus a time-centred constant-gravity source,
+ *   A9 (optional) passively advected species, carried by the mass fluxes of
+ *      the three rounds.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no -ffast-math).
  */
@@ -117,9 +119,10 @@ static int ghost_src(int g, int n, int bc_lo, int bc_hi, int *flip)
     }
 }
 
-int orc_fill_ghosts(double *U, const orc_box *b)
+/* fill the ghosts of nc components; hydro: component 1+d is the
+ * d-momentum, whose sign a reflecting face flips */
+static void fill_comps(double *U, const orc_box *b, int nc, int hydro)
 {
-    if (!U || !box_ok(b)) return -1;
     long long s[3];
     extents(b, s);
     const long long cs = s[0] * s[1] * s[2];
@@ -143,13 +146,26 @@ int orc_fill_ghosts(double *U, const orc_box *b)
                                          b->bc_hi[d], &flip);
                         long long dst = cidx(s, ng, p[0], p[1], p[2]);
                         long long src = cidx(s, ng, q[0], q[1], q[2]);
-                        for (int c = 0; c < 5; ++c) {
+                        for (int c = 0; c < nc; ++c) {
                             double v = U[c * cs + src];
-                            U[c * cs + dst] = (flip && c == 1 + d) ? -v : v;
+                            U[c * cs + dst] = (hydro && flip && c == 1 + d) ? -v : v;
                         }
                     }
         }
     }
+}
+
+int orc_fill_ghosts(double *U, const orc_box *b)
+{
+    if (!U || !box_ok(b)) return -1;
+    fill_comps(U, b, 5, 1);
+    return 0;
+}
+
+int orc_fill_ghosts_species(double *S, int nspec, const orc_box *b)
+{
+    if (!S || nspec < 1 || nspec > ORC_MAX_SPECIES || !box_ok(b)) return -1;
+    fill_comps(S, b, nspec, 0);
     return 0;
 }
 
@@ -589,11 +605,14 @@ static int accept_state(const double V[5], const double q[5], double gm1,
 /* one step on an output region                                        */
 /* ------------------------------------------------------------------ */
 
-int orc_advance_region(const double *U, double *Unew, const orc_box *b,
-                       const orc_params *pr, double dt, const int lo[3],
-                       const int hi[3], int *errp)
+/* One step of the hydro state U and, when nspec > 0, of the nspec partial
+ * densities S (rho X_s, same layout, ghosts filled) into Snew. */
+static int advance(const double *U, double *Unew, const double *S, double *Snew,
+                   int nspec, const orc_box *b, const orc_params *pr, double dt,
+                   const int lo[3], const int hi[3], int *errp)
 {
     if (!U || !Unew || !pr || !errp || !box_ok(b)) return -1;
+    if (nspec < 0 || nspec > ORC_MAX_SPECIES || (nspec > 0 && (!S || !Snew))) return -1;
     for (int d = 0; d < 3; ++d)
         if (lo[d] < 0 || hi[d] > b->n[d] || lo[d] >= hi[d]) return -1;
 
@@ -618,6 +637,13 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
     }
 
     fld prim, fl, qhi[3], qlo[3], F1[3], F2[3][3], F3[3];
+    fld X, Xhi[3], Xlo[3], G1[3], G2[3][3], G3[3]; /* species (A9) */
+    memset(&X, 0, sizeof X);
+    memset(Xhi, 0, sizeof Xhi);
+    memset(Xlo, 0, sizeof Xlo);
+    memset(G1, 0, sizeof G1);
+    memset(G2, 0, sizeof G2);
+    memset(G3, 0, sizeof G3);
     memset(&prim, 0, sizeof prim);
     memset(&fl, 0, sizeof fl);
     memset(qhi, 0, sizeof qhi);
@@ -818,18 +844,173 @@ int orc_advance_region(const double *U, double *Unew, const orc_box *b,
 
     ORC_STAGE_MARK(8);
 
+    /* A9: passively advected species.  A species is carried by the gas: its
+     * flux through a face is the mass flux there times the mass fraction X
+     * of the cell the mass comes from (the face state on the side the mass
+     * flux leaves, the low side when it is zero).  Its face values are traced
+     * like a transverse velocity -- it changes only across the contact wave
+     * -- and corrected like the density: X of a corrected state is the
+     * corrected partial density over the corrected density, each formed from
+     * the same flux differences, the traced X kept where that density is not
+     * positive. */
+    if (nspec > 0) {
+        const int ns = nspec;
+        if (!fld_make(&X, g3lo, g3hi, ns)) { rc = -2; goto done; }
+        FOR_REGION(g3lo, g3hi, p, {
+            long long o = cidx(s, ng, p[0], p[1], p[2]);
+            const double rho = fat(&prim, p)[0];
+            for (int c = 0; c < ns; ++c) fat(&X, p)[c] = S[c * cs + o] / rho;
+        })
+        for (int d = 0; d < 3; ++d) {
+            if (!fld_make(&Xhi[d], g1lo, g1hi, ns) || !fld_make(&Xlo[d], g1lo, g1hi, ns)) {
+                rc = -2;
+                goto done;
+            }
+            const double dtdx = dt / b->dx[d];
+            FOR_REGION(g1lo, g1hi, p, {
+                const double un = fat(&prim, p)[1 + d], c = fat(&prim, p)[5];
+                const double f = flat ? fat(&fl, p)[0] : 1.0;
+                for (int sp = 0; sp < ns; ++sp) {
+                    double a[5], aL, aR;
+                    for (int m = 0; m < 5; ++m) {
+                        int r[3] = {p[0], p[1], p[2]};
+                        r[d] += m - 2;
+                        a[m] = fat(&X, r)[sp];
+                    }
+                    ppm_faces(a, f, &aL, &aR);
+                    fat(&Xhi[d], p)[sp] = edge_hi(a[2], aL, aR, un > 0.0 ? un : un + c, dtdx);
+                    fat(&Xlo[d], p)[sp] = edge_lo(a[2], aL, aR, un < 0.0 ? un : un - c, dtdx);
+                }
+            })
+        }
+        /* round 1 */
+        for (int d = 0; d < 3; ++d) {
+            if (!fld_make(&G1[d], F1[d].lo, F1[d].hi, ns)) { rc = -2; goto done; }
+            FOR_REGION(F1[d].lo, F1[d].hi, p, {
+                int l[3] = {p[0], p[1], p[2]};
+                l[d] -= 1;
+                const double F = fat(&F1[d], p)[0];
+                for (int sp = 0; sp < ns; ++sp)
+                    fat(&G1[d], p)[sp] = F * (F >= 0.0 ? fat(&Xhi[d], l)[sp] : fat(&Xlo[d], p)[sp]);
+            })
+        }
+        /* round 2: corner-coupled states (dt/3 of one transverse difference) */
+        for (int t = 0; t < 3; ++t)
+            for (int sd = 0; sd < 3; ++sd) {
+                if (sd == t) continue;
+                const fld *Fm = &F2[t][sd];
+                if (!fld_make(&G2[t][sd], Fm->lo, Fm->hi, ns)) { rc = -2; goto done; }
+                const double fac = dt / (3.0 * b->dx[sd]);
+                FOR_REGION(Fm->lo, Fm->hi, p, {
+                    int cl[3] = {p[0], p[1], p[2]}, cr[3] = {p[0], p[1], p[2]};
+                    cl[t] -= 1;
+                    double xc[2][ORC_MAX_SPECIES];
+                    for (int side = 0; side < 2; ++side) {
+                        const int *c = side ? cr : cl;
+                        int cu[3] = {c[0], c[1], c[2]};
+                        cu[sd] += 1;
+                        const double rq = side ? fat(&qlo[t], c)[0] : fat(&qhi[t], c)[0];
+                        const double *xq = side ? fat(&Xlo[t], c) : fat(&Xhi[t], c);
+                        const double den = rq - fac * (fat(&F1[sd], cu)[0] - fat(&F1[sd], c)[0]);
+                        for (int sp = 0; sp < ns; ++sp) {
+                            const double num =
+                                rq * xq[sp] - fac * (fat(&G1[sd], cu)[sp] - fat(&G1[sd], c)[sp]);
+                            xc[side][sp] = den > 0.0 ? num / den : xq[sp];
+                        }
+                    }
+                    const double F = fat(Fm, p)[0];
+                    for (int sp = 0; sp < ns; ++sp)
+                        fat(&G2[t][sd], p)[sp] = F * (F >= 0.0 ? xc[0][sp] : xc[1][sp]);
+                })
+            }
+        /* round 3: final states (dt/2 of both round-2 transverse differences) */
+        for (int d = 0; d < 3; ++d) {
+            int t1, t2;
+            transverse(d, &t1, &t2);
+            if (!fld_make(&G3[d], F3[d].lo, F3[d].hi, ns)) { rc = -2; goto done; }
+            const double f1 = dt / (2.0 * b->dx[t1]);
+            const double f2 = dt / (2.0 * b->dx[t2]);
+            FOR_REGION(F3[d].lo, F3[d].hi, p, {
+                int cl[3] = {p[0], p[1], p[2]}, cr[3] = {p[0], p[1], p[2]};
+                cl[d] -= 1;
+                double xf[2][ORC_MAX_SPECIES];
+                for (int side = 0; side < 2; ++side) {
+                    const int *c = side ? cr : cl;
+                    int c1[3] = {c[0], c[1], c[2]}, c2[3] = {c[0], c[1], c[2]};
+                    c1[t1] += 1;
+                    c2[t2] += 1;
+                    const double rq = side ? fat(&qlo[d], c)[0] : fat(&qhi[d], c)[0];
+                    const double *xq = side ? fat(&Xlo[d], c) : fat(&Xhi[d], c);
+                    const double den = (rq - f1 * (fat(&F2[t1][t2], c1)[0] - fat(&F2[t1][t2], c)[0])) -
+                                       f2 * (fat(&F2[t2][t1], c2)[0] - fat(&F2[t2][t1], c)[0]);
+                    for (int sp = 0; sp < ns; ++sp) {
+                        const double num =
+                            (rq * xq[sp] - f1 * (fat(&G2[t1][t2], c1)[sp] - fat(&G2[t1][t2], c)[sp])) -
+                            f2 * (fat(&G2[t2][t1], c2)[sp] - fat(&G2[t2][t1], c)[sp]);
+                        xf[side][sp] = den > 0.0 ? num / den : xq[sp];
+                    }
+                }
+                const double F = fat(&F3[d], p)[0];
+                for (int sp = 0; sp < ns; ++sp)
+                    fat(&G3[d], p)[sp] = F * (F >= 0.0 ? xf[0][sp] : xf[1][sp]);
+            })
+        }
+        /* conservative update of the partial densities */
+        {
+            const double dtdx[3] = {dt / b->dx[0], dt / b->dx[1], dt / b->dx[2]};
+            FOR_REGION(lo, hi, p, {
+                long long o = cidx(s, ng, p[0], p[1], p[2]);
+                int px[3] = {p[0] + 1, p[1], p[2]};
+                int py[3] = {p[0], p[1] + 1, p[2]};
+                int pz[3] = {p[0], p[1], p[2] + 1};
+                for (int sp = 0; sp < ns; ++sp) {
+                    double du = dtdx[0] * (fat(&G3[0], px)[sp] - fat(&G3[0], p)[sp]);
+                    du = du + dtdx[1] * (fat(&G3[1], py)[sp] - fat(&G3[1], p)[sp]);
+                    du = du + dtdx[2] * (fat(&G3[2], pz)[sp] - fat(&G3[2], p)[sp]);
+                    const double v = S[sp * cs + o] - du;
+                    if (!isfinite(v)) err |= ORC_ERR_NONFINITE;
+                    Snew[sp * cs + o] = v;
+                }
+            })
+        }
+    }
+
 done:
     free(prim.v);
     free(fl.v);
+    free(X.v);
     for (int d = 0; d < 3; ++d) {
         free(qhi[d].v);
         free(qlo[d].v);
         free(F1[d].v);
         free(F3[d].v);
-        for (int e = 0; e < 3; ++e) free(F2[d][e].v);
+        free(Xhi[d].v);
+        free(Xlo[d].v);
+        free(G1[d].v);
+        free(G3[d].v);
+        for (int e = 0; e < 3; ++e) {
+            free(F2[d][e].v);
+            free(G2[d][e].v);
+        }
     }
     *errp |= err;
     return rc;
+}
+
+int orc_advance_region(const double *U, double *Unew, const orc_box *b,
+                       const orc_params *pr, double dt, const int lo[3],
+                       const int hi[3], int *errp)
+{
+    return advance(U, Unew, NULL, NULL, 0, b, pr, dt, lo, hi, errp);
+}
+
+int orc_advance_region_species(const double *U, double *Unew, const double *S,
+                               double *Snew, int nspec, const orc_box *b,
+                               const orc_params *pr, double dt, const int lo[3],
+                               const int hi[3], int *errp)
+{
+    if (nspec < 1) return -1;
+    return advance(U, Unew, S, Snew, nspec, b, pr, dt, lo, hi, errp);
 }
 
 int orc_advance_box(const double *U, double *Unew, const orc_box *b,

@@ -65,6 +65,8 @@ typedef struct {
                        flattening of every cell (coefficient 0; a test mode) */
 } orc_params;
 
+#define ORC_MAX_SPECIES 8
+
 /* Number of doubles of one state array (all five components, with ghosts). */
 long long orc_state_elems(const orc_box *b);
 
@@ -88,6 +90,20 @@ int orc_estimate_dt(const double *U, const orc_box *b, const orc_params *p,
 int orc_advance_region(const double *U, double *Unew, const orc_box *b,
                        const orc_params *p, double dt, const int lo[3],
                        const int hi[3], int *err);
+
+/* orc_advance_region with nspec passively advected species as well
+ * (1 <= nspec <= ORC_MAX_SPECIES): S holds their partial densities rho X_s
+ * in the state layout (nspec components, ghosts filled); Snew receives them
+ * on the output region.  U and Unew are as in orc_advance_region, whose
+ * results this function reproduces bit for bit. */
+int orc_advance_region_species(const double *U, double *Unew, const double *S,
+                               double *Snew, int nspec, const orc_box *b,
+                               const orc_params *p, double dt, const int lo[3],
+                               const int hi[3], int *err);
+
+/* Ghost fill of nspec species components, by the rules of orc_fill_ghosts
+ * without any sign flip.  Returns 0 or -1. */
+int orc_fill_ghosts_species(double *S, int nspec, const orc_box *b);
 
 /* orc_advance_region over the whole valid box. */
 int orc_advance_box(const double *U, double *Unew, const orc_box *b,

@@ -70,6 +70,9 @@ def _load(path):
         L.orc_estimate_dt.argtypes = [dp, bp, pp, dp]
         L.orc_advance_region.argtypes = [dp, dp, bp, pp, C.c_double, ip, ip, ip]
         L.orc_advance_box.argtypes = [dp, dp, bp, pp, C.c_double, ip]
+        L.orc_advance_region_species.argtypes = [dp, dp, dp, dp, C.c_int, bp, pp, C.c_double,
+                                                 ip, ip, ip]
+        L.orc_fill_ghosts_species.argtypes = [dp, C.c_int, bp]
         L.orc_ppm_parabola.argtypes = [dp, dp]
         L.orc_ppm_parabola_flat.argtypes = [dp, C.c_double, dp]
         L.orc_flatten_1d.argtypes = [dp, dp]
@@ -141,6 +144,46 @@ def advance_region(U, Unew, box, prm, dt, lo, hi):
 
 def advance_box(U, Unew, box, prm, dt):
     return advance_region(U, Unew, box, prm, dt, (0, 0, 0), tuple(box.n))
+
+
+# ---- passively advected species: S has shape (nspec, ...) in the state
+# layout and holds the partial densities rho X_s
+
+def fill_ghosts_species(S, box):
+    if lib().orc_fill_ghosts_species(_dp(S), S.shape[0], C.byref(box)) != 0:
+        raise ValueError("orc_fill_ghosts_species: invalid arguments")
+
+
+def advance_region_species(U, Unew, S, Snew, box, prm, dt, lo, hi):
+    err = C.c_int(0)
+    lo_a = (C.c_int * 3)(*lo)
+    hi_a = (C.c_int * 3)(*hi)
+    assert S.shape == Snew.shape and S.shape[1:] == U.shape[1:]
+    rc = lib().orc_advance_region_species(_dp(U), _dp(Unew), _dp(S), _dp(Snew), S.shape[0],
+                                          C.byref(box), C.byref(prm), dt, lo_a, hi_a,
+                                          C.byref(err))
+    if rc == -2:
+        raise MemoryError("oracle: out of memory")
+    if rc != 0:
+        raise ValueError("orc_advance_region_species: invalid arguments")
+    return err.value
+
+
+def advance_box_species(U, Unew, S, Snew, box, prm, dt):
+    return advance_region_species(U, Unew, S, Snew, box, prm, dt, (0, 0, 0), tuple(box.n))
+
+
+def step_species(U, S, box, prm):
+    """One whole step of the gas and its species: ghost fill of both, CFL dt
+    (from the gas), advance.  Returns (Unew, Snew, dt, err)."""
+    U = np.ascontiguousarray(U)
+    S = np.ascontiguousarray(S)
+    fill_ghosts(U, box)
+    fill_ghosts_species(S, box)
+    dt = estimate_dt(U, box, prm)
+    Unew, Snew = U.copy(), S.copy()
+    err = advance_box_species(U, Unew, S, Snew, box, prm, dt)
+    return Unew, Snew, dt, err
 
 
 def step(U, box, prm, slab=None):

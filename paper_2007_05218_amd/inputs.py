@@ -187,6 +187,32 @@ def uniform(n, rho=1.0, vel=(0.3, -0.2, 0.1), p=1.0, bc=BC_PERIODIC, ng=NG):
     return from_primitive(box, rho, vel[0], vel[1], vel[2], p), box, params_desc()
 
 
+def species(U, box, nspec=2, seed=5):
+    """Partial densities rho X_s (shape (nspec,) + the state's spatial shape,
+    ghosts included) of nspec mass fractions that sum to one: species 0 is
+    the gas denser than the box's mean density (a sharp interface wherever
+    the flow has one), the others share the rest in proportions set by
+    seeded smooth random fields, 1 + 0.5 S_s."""
+    ng, n = box["ng"], box["n"]
+    rho = U[0]
+    X = np.empty((nspec,) + rho.shape)
+    heavy = (rho > rho[ng:ng + n[2], ng:ng + n[1], ng:ng + n[0]].mean()).astype(np.float64)
+    if nspec == 1:
+        X[0] = heavy
+    else:
+        X[0] = heavy
+        full = box_desc(tuple(v + 2 * ng for v in n), 0, dx=box["dx"])
+        L = [full["n"][d] * box["dx"][d] for d in range(3)]
+        xyz = cell_centres(full)
+        kids = np.random.SeedSequence(seed).spawn(nspec - 1)
+        w = [np.broadcast_to(1.0 + 0.5 * _modes(np.random.default_rng(k), full["n"], L, xyz),
+                             rho.shape) for k in kids]
+        tot = sum(w)
+        for s in range(1, nspec):
+            X[s] = (1.0 - heavy) * (w[s - 1] / tot)
+    return np.ascontiguousarray(rho[None] * X)
+
+
 def sedov(n=64, r0_cells=2.0, p_amb=1e-5, e_blast=1.0, ng=NG):
     """Point blast (Sedov-Taylor) in the unit cube: rho = 1, at rest, pressure
     p_amb, except the cells whose centres lie within r0_cells cell widths of

@@ -1,8 +1,8 @@
 """The pins catch plausible mistakes: each mutant below is the oracle's source
 with one deliberate error (a flipped sign, a dropped term, a wrong constant
 or operand), compiled on the CPU; the battery of pins of
-test_oracle_pieces.py / test_oracle_scheme.py / test_oracle_flatten.py is run
-against it and at least
+test_oracle_pieces.py / test_oracle_scheme.py / test_oracle_flatten.py /
+test_oracle_species.py is run against it and at least
 one pin must fail.  Nothing here touches a GPU."""
 import os
 import subprocess
@@ -13,6 +13,7 @@ import pytest
 import test_oracle_flatten as F
 import test_oracle_pieces as P
 import test_oracle_scheme as S
+import test_oracle_species as SP
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
@@ -34,7 +35,7 @@ MUTANTS = {
         "double SR = mx(uL + cL, uR + cR);",
         "double SR = mn(uL + cL, uR + cR);"),
     "reflect without momentum flip": (
-        "U[c * cs + dst] = (flip && c == 1 + d) ? -v : v;",
+        "U[c * cs + dst] = (hydro && flip && c == 1 + d) ? -v : v;",
         "U[c * cs + dst] = v;"),
     "z flux divergence sign": (
         "du = du + dtdx[2] * (fat(&F3[2], pz)[v] - fat(&F3[2], p)[v]);",
@@ -72,6 +73,21 @@ MUTANTS = {
     "flattening weights swapped": (
         "aL = f * aL + (1.0 - f) * ac;",
         "aL = (1.0 - f) * aL + f * ac;"),
+    "species donor side swapped": (
+        "fat(&G1[d], p)[sp] = F * (F >= 0.0 ? fat(&Xhi[d], l)[sp] : fat(&Xlo[d], p)[sp]);",
+        "fat(&G1[d], p)[sp] = F * (F >= 0.0 ? fat(&Xlo[d], p)[sp] : fat(&Xhi[d], l)[sp]);"),
+    "species traced on the fast wave": (
+        "un > 0.0 ? un : un + c",
+        "un + c"),
+    "species corner correction sign": (
+        "rq * xq[sp] - fac * (fat(&G1[sd], cu)[sp] - fat(&G1[sd], c)[sp]);",
+        "rq * xq[sp] + fac * (fat(&G1[sd], cu)[sp] - fat(&G1[sd], c)[sp]);"),
+    "species final correction operand": (
+        "f2 * (fat(&G2[t2][t1], c2)[sp] - fat(&G2[t2][t1], c)[sp]);",
+        "f2 * (fat(&G2[t2][t1], c1)[sp] - fat(&G2[t2][t1], c)[sp]);"),
+    "species update y-difference sign": (
+        "du = du + dtdx[1] * (fat(&G3[1], py)[sp] - fat(&G3[1], p)[sp]);",
+        "du = du - dtdx[1] * (fat(&G3[1], py)[sp] - fat(&G3[1], p)[sp]);"),
     "flattening steepness threshold": (
         "double chi = mn(1.0, mx(0.0, FL_W2 * (z - FL_W1)));",
         "double chi = mn(1.0, mx(0.0, FL_W2 * (z - 0.5)));"),
@@ -106,6 +122,12 @@ BATTERY = [
     ("flattening toward the mean", lambda o: F.test_flattening_limits_the_parabola_toward_the_mean(o)),
     ("full flattening first order", lambda o: F.test_full_flattening_is_first_order(o)),
     ("strong shock marked", lambda o: F.test_coefficient_marks_a_strong_shock_only(o)),
+    ("species unit fraction", lambda o: [SP.test_unit_fraction_is_the_density_bitwise(o, c)
+                                         for c in ("kh", "rt")]),
+    ("species 1-D advection", lambda o: [SP.test_uniform_flow_is_1d_ppm_advection(o, a, u)
+                                         for a in (0, 1, 2) for u in (0.6, -1.7)]),
+    ("species CTU advection", lambda o: [SP.test_oblique_uniform_flow_is_ctu_advection(o, v)
+                                         for v in ((0.7, -0.5, 0.4), (-1.6, 0.3, -0.9))]),
 ]
 
 

@@ -1,0 +1,242 @@
+"""Pins of the oracle's passively advected species (CPU only).
+
+What fixes the species update independently of its own code:
+  * a species whose mass fraction is one everywhere is the gas itself: its
+    partial density must equal the density after every step, bit for bit
+    (every numerator of the species pipeline equals the matching density
+    denominator, and every species flux equals the mass flux);
+  * the gas is not touched by the species: the hydro state equals the
+    species-free step's bit for bit;
+  * in a uniform gas moving along one axis the species update reduces to
+    the one-dimensional PPM advection of a scalar (Colella & Woodward 1984,
+    Sec. 1), written out below with numpy; moving obliquely, to the
+    corner-transport-upwind advection of a scalar (Colella 1990; Saltzman
+    1994 in three dimensions) built from the same one-dimensional pieces,
+    written in its compact Courant-number form;
+  * a constant fraction stays constant, and each species' total is
+    conserved on a periodic box (fractions that sum to one need not keep
+    summing to one exactly: the PPM limiter is not linear);
+  * the result on a cell does not depend on the region it is computed in.
+"""
+import numpy as np
+import pytest
+
+from paper_2007_05218_amd import inputs
+
+
+def _steps(orc, U, S, box, prm, n):
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    err = 0
+    for _ in range(n):
+        U, S, dt, e = orc.step_species(U, S, ob, op)
+        err |= e
+    return U, S, err
+
+
+CASES = {
+    "kh": lambda: inputs.kh(20, seed=1),
+    "rt": lambda: inputs.rt((12, 12, 24), seed=4),
+    "sod_reflect_y": lambda: inputs.sod((6, 24, 6), axis=1, mirror=True),
+    "sedov_flat": lambda: (lambda U, b, p: (U, b, dict(p, flatten=1)))(*inputs.sedov(16)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_unit_fraction_is_the_density_bitwise(orc, case):
+    U, box, prm = CASES[case]()
+    S = np.ascontiguousarray(np.stack([U[0], 0.25 * U[0]]))
+    U1, S1, err = _steps(orc, U, S, box, prm, 6)
+    V = inputs.valid
+    assert np.array_equal(V(S1, box)[0], V(U1, box)[0])
+    # a constant fraction stays constant (to rounding)
+    assert np.abs(V(S1, box)[1] / V(U1, box)[0] - 0.25).max() < 1e-14
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_gas_unchanged_by_species(orc, case):
+    U, box, prm = CASES[case]()
+    S = inputs.species(U, box, 3, seed=7)
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    Ua, Sa, dta, ea = orc.step_species(U, S, ob, op)
+    Ub, dtb, eb = orc.step(U, ob, op)
+    assert dta == dtb and ea == eb
+    assert np.array_equal(inputs.valid(Ua, box), inputs.valid(Ub, box))
+
+
+def _ppm_upwind_faces(a, sigma, axis):
+    """Along ``axis`` of a periodic array: each cell's limited parabola
+    averaged over the part that crosses its downstream face in one step
+    (Courant number sigma), i.e. the value it sends through that face."""
+    r = lambda v, k: np.roll(v, k, axis=axis)
+    am, ap = r(a, 1), r(a, -1)
+    dl, dr, dc = a - am, ap - a, 0.5 * (ap - am)
+    lim = np.minimum(np.minimum(np.abs(dc), 2 * np.abs(dl)), 2 * np.abs(dr))
+    d = np.where(dl * dr > 0, np.copysign(lim, dc), 0.0)
+    face = 0.5 * (a + ap) - (r(d, -1) - d) / 6.0
+    aR, aL = face.copy(), r(face, 1)
+    flat = (aR - a) * (a - aL) <= 0
+    aL, aR = np.where(flat, a, aL), np.where(flat, a, aR)
+    dA, m = aR - aL, a - 0.5 * (aL + aR)
+    over_l = dA * m > dA * dA / 6.0
+    over_r = -(dA * dA) / 6.0 > dA * m
+    aL = np.where(over_l, 3 * a - 2 * aR, aL)
+    aR = np.where(~over_l & over_r, 3 * a - 2 * aL, aR)
+    dA, a6 = aR - aL, 6.0 * (a - 0.5 * (aL + aR))
+    s = abs(sigma)
+    if sigma > 0:
+        return aR - 0.5 * s * (dA - (1 - 2 * s / 3) * a6)
+    return aL + 0.5 * s * (dA + (1 - 2 * s / 3) * a6)
+
+
+def _ctu_advect_3d(a, sig):
+    """One corner-transport-upwind step of a_t + u.grad a = 0 on a periodic
+    (z, y, x) array, Courant numbers sig[d] along x, y, z.  D[d] holds each
+    cell's upwind-sent value along d; div(d, D) is the Courant-weighted
+    difference of those values across the cell.  Corner values are the
+    one-dimensional ones corrected by a third of one transverse difference,
+    final values by half of both corner-coupled transverse differences."""
+    ax = lambda d: 2 - d
+
+    def div(d, D):
+        if sig[d] > 0:
+            return sig[d] * (D - np.roll(D, 1, axis=ax(d)))
+        return sig[d] * (np.roll(D, -1, axis=ax(d)) - D)
+
+    D1 = [_ppm_upwind_faces(a, sig[d], ax(d)) for d in range(3)]
+    D2 = {(d, t): D1[d] - div(t, D1[t]) / 3.0 for d in range(3) for t in range(3) if t != d}
+    out = a.copy()
+    for d in range(3):
+        t1, t2 = [t for t in range(3) if t != d]
+        D3 = D1[d] - 0.5 * div(t1, D2[(t1, t2)]) - 0.5 * div(t2, D2[(t2, t1)])
+        out = out - div(d, D3)
+    return out
+
+
+def _ppm_advect_1d(a, sigma):
+    """One step of the PPM scheme for a_t + u a_x = 0 on a periodic line,
+    Courant number sigma = u dt/dx (either sign): limited parabolae from
+    monotonised-central slopes and fourth-order interface values, the
+    parabola limiter, and the parabola averaged over the part of the upwind
+    cell that crosses each interface."""
+    am, ap = np.roll(a, 1), np.roll(a, -1)
+    dl, dr, dc = a - am, ap - a, 0.5 * (ap - am)
+    lim = np.minimum(np.minimum(np.abs(dc), 2 * np.abs(dl)), 2 * np.abs(dr))
+    d = np.where(dl * dr > 0, np.copysign(lim, dc), 0.0)
+    face = 0.5 * (a + ap) - (np.roll(d, -1) - d) / 6.0    # value at i+1/2
+    aR, aL = face.copy(), np.roll(face, 1)
+    flat = (aR - a) * (a - aL) <= 0
+    aL, aR = np.where(flat, a, aL), np.where(flat, a, aR)
+    dA, m = aR - aL, a - 0.5 * (aL + aR)
+    over_l = dA * m > dA * dA / 6.0
+    over_r = -(dA * dA) / 6.0 > dA * m
+    aL = np.where(over_l, 3 * a - 2 * aR, aL)
+    aR = np.where(~over_l & over_r, 3 * a - 2 * aL, aR)
+    dA, a6 = aR - aL, 6.0 * (a - 0.5 * (aL + aR))
+    s = abs(sigma)
+    if sigma > 0:   # interface i+1/2 takes cell i's right part
+        F = aR - 0.5 * s * (dA - (1 - 2 * s / 3) * a6)
+    else:           # ... or cell i+1's left part
+        Fl = aL + 0.5 * s * (dA + (1 - 2 * s / 3) * a6)
+        F = np.roll(Fl, -1)
+    return a - sigma * (F - np.roll(F, 1))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("u", [0.6, -0.6, 1.7, -1.7])
+def test_uniform_flow_is_1d_ppm_advection(orc, axis, u):
+    # rho = 1 everywhere, so rho X = X; a fraction profile with a step and a
+    # smooth part along the axis, advected by the flow along it (subsonic and
+    # supersonic speeds, both signs)
+    n = [4, 4, 4]
+    n[axis] = 40
+    vel = [0.0, 0.0, 0.0]
+    vel[axis] = u
+    U, box, prm = inputs.uniform(tuple(n), rho=1.0, vel=tuple(vel), p=1.0)
+    xs = (np.arange(40) + 0.5) / 40
+    prof = np.where((xs > 0.3) & (xs < 0.55), 1.0, 0.2) + 0.3 * np.sin(2 * np.pi * xs) ** 2
+    ng = box["ng"]
+    shape = [1, 1, 1]
+    shape[2 - axis] = 40
+    S = np.zeros((1,) + U.shape[1:])
+    inputs.valid(S, box)[0] = prof.reshape(shape)
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    a = prof.copy()
+    for _ in range(8):
+        U, S, dt, err = orc.step_species(U, S, ob, op)
+        a = _ppm_advect_1d(a, u * dt / box["dx"][axis])
+        assert err == 0
+    got = np.moveaxis(inputs.valid(S, box)[0], 2 - axis, 0)
+    for line in got.reshape(40, -1).T:
+        assert np.abs(line - a).max() < 1e-13
+
+
+@pytest.mark.parametrize("vel", [(0.7, -0.5, 0.4), (-1.6, 0.3, -0.9)])
+def test_oblique_uniform_flow_is_ctu_advection(orc, vel):
+    n = (12, 10, 8)
+    U, box, prm = inputs.uniform(n, rho=1.0, vel=vel, p=1.0)
+    rng = np.random.default_rng(21)
+    X0 = rng.uniform(0.0, 1.0, size=(n[2], n[1], n[0]))
+    X0[2:5, 3:7, 4:9] = 1.5   # a block with sharp edges
+    S = np.zeros((1,) + U.shape[1:])
+    inputs.valid(S, box)[0] = X0
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    a = X0.copy()
+    for _ in range(5):
+        U, S, dt, err = orc.step_species(U, S, ob, op)
+        a = _ctu_advect_3d(a, [vel[d] * dt / box["dx"][d] for d in range(3)])
+        assert err == 0
+    assert np.abs(inputs.valid(S, box)[0] - a).max() < 1e-12
+
+
+def test_species_conserved_periodic(orc):
+    U, box, prm = CASES["kh"]()   # periodic on every axis: nothing leaves
+    S = inputs.species(U, box, 3, seed=7)
+    V = inputs.valid
+    tot0 = V(S, box).sum(axis=(1, 2, 3))
+    U1, S1, err = _steps(orc, U, S, box, prm, 8)
+    tot1 = V(S1, box).sum(axis=(1, 2, 3))
+    assert np.allclose(tot1, tot0, rtol=1e-13, atol=0)
+    # and the fractions stay near the range they started in
+    X = V(S1, box) / V(U1, box)[0]
+    assert X.min() > -0.05 and X.max() < 1.05
+
+
+def test_region_independence(orc):
+    U, box, prm = inputs.kh((18, 14, 10), seed=3)
+    S = inputs.species(U, box, 2, seed=9)
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    orc.fill_ghosts(U, ob)
+    orc.fill_ghosts_species(S, ob)
+    dt = orc.estimate_dt(U, ob, op)
+    Ua, Sa = U.copy(), S.copy()
+    orc.advance_box_species(U, Ua, S, Sa, ob, op, dt)
+    Ub, Sb = U.copy(), S.copy()
+    for lo, hi in [((0, 0, 0), (7, 14, 10)), ((7, 0, 0), (18, 5, 10)), ((7, 5, 0), (18, 14, 4)),
+                   ((7, 5, 4), (18, 14, 10))]:
+        orc.advance_region_species(U, Ub, S, Sb, ob, op, dt, lo, hi)
+    assert np.array_equal(inputs.valid(Sa, box), inputs.valid(Sb, box))
+    assert np.array_equal(inputs.valid(Ua, box), inputs.valid(Ub, box))
+
+
+def test_species_ghost_fill_is_the_density_fill(orc):
+    # species ghosts follow the density's rules (no sign flip at reflecting
+    # faces): filling the density slot and the species array agree
+    for bc in (inputs.BC_PERIODIC, inputs.BC_OUTFLOW, inputs.BC_REFLECT):
+        U, box, prm = inputs.uniform((7, 6, 5), bc=bc)
+        rng = np.random.default_rng(11)
+        inputs.valid(U, box)[0] = rng.uniform(0.5, 1.5, size=(5, 6, 7))
+        S = np.ascontiguousarray(np.stack([U[0], 2.0 * U[0]]))
+        ob = orc.box_from(box)
+        orc.fill_ghosts(U, ob)
+        orc.fill_ghosts_species(S, ob)
+        assert np.array_equal(S[0], U[0]) and np.array_equal(S[1], 2.0 * U[0])
+
+
+def test_invalid_species_arguments_rejected(orc):
+    U, box, prm = inputs.kh(8, seed=1)
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    S = np.zeros((9,) + U.shape[1:])   # more than the oracle's 8
+    with pytest.raises(ValueError):
+        orc.fill_ghosts_species(S, ob)
+    with pytest.raises(ValueError):
+        orc.advance_box_species(U, U.copy(), S, S.copy(), ob, op, 1e-3)
