@@ -135,6 +135,43 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
                          const hydro_params *prm, const double *dt_dev, double *dt_next_dev,
                          void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream);
 
+/* Passively advected species (the multi-component fluid state of Sec. II's
+ * Fabs; the isotopes a reaction network follows, Sec. IV-B): nspec mass
+ * fractions X_s (1 <= nspec <= 8) carried by the gas, held as partial
+ * densities rho X_s in their own array: nspec components in the state
+ * layout (component s at offset s * s0 s1 s2 doubles).
+ *
+ * Species workspace, in bytes, that advance_box_species needs for this box
+ * and species count (the mass fluxes of the gas step and the species
+ * pass's face values); 0 for invalid arguments. */
+size_t hydro_species_workspace_bytes(const hydro_box *box, int nspec);
+
+/* Ghost fill of the species array S_dev by the rules of hydro_fill_ghosts,
+ * with no sign flip at reflecting faces.  In place. */
+hydro_status hydro_fill_ghosts_species(double *S_dev, int nspec, const hydro_box *box,
+                                       void *stream);
+
+/* advance_box, plus the same step for the species: S_new_dev receives the
+ * valid cells of rho X_s after the step, from S_dev (ghosts filled).  The gas
+ * arguments and results are exactly those of advance_box (its new state is
+ * identical bit for bit).  Through every face the species flux is the mass
+ * flux of the same Riemann solve times the mass fraction of the side the
+ * mass leaves (the low side for a zero flux); face values of X are traced
+ * like a transverse velocity (they change across the contact wave only), and
+ * corrected like the density: each transverse-corrected X is the corrected
+ * partial density over the corrected density, formed from the same flux
+ * differences, the traced X kept where that density is not positive.
+ * sws_dev (sws_bytes >= hydro_species_workspace_bytes(box, nspec), else
+ * HYDRO_ENOWS; 256-byte aligned) is scratch whose contents on entry do not
+ * matter.  S_new_dev must not overlap S_dev, the gas states or the
+ * workspaces, nor the species workspace any array (HYDRO_EINVAL).  A
+ * non-finite new partial density raises error bit 1. */
+hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const double *S_dev,
+                                 double *S_new_dev, int nspec, const hydro_box *box,
+                                 const hydro_params *prm, const double *dt_dev,
+                                 double *dt_next_dev, void *ws_dev, size_t ws_bytes,
+                                 void *sws_dev, size_t sws_bytes, int32_t *err_dev, void *stream);
+
 /* Batched timestep over a list of boxes (a level of Sec. II's MultiFab):
  * fills the ghosts of every box, writes each box's dt to dt_dev[b] and, if
  * dt_min_dev is not NULL, the minimum over boxes to *dt_min_dev.

@@ -278,8 +278,15 @@ __device__ __forceinline__ Flux next_minus(const Flux &f)
 #ifndef HYDRO_FUSED_WAVES
 #define HYDRO_FUSED_WAVES 2
 #endif
+// EX: also export the mass flux of every Riemann solve the box step makes
+// (twelve fields, one per flux family, over faces named by the cell above,
+// coordinates -1 .. n per axis) for the species pass.  A tile stores a flux
+// only where it computed it from valid data; tiles that overlap store the
+// same value.
+template <bool EX>
 __global__ void __launch_bounds__(kFT) __attribute__((amdgpu_waves_per_eu(HYDRO_FUSED_WAVES)))
-k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz, int *err_dev)
+k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz, int *err_dev,
+             double *mflux)
 {
     // y-neighbour exchanges alternate between two buffers, so each needs one
     // barrier (its readers of two exchanges back are past the barrier of the
@@ -320,6 +327,12 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
                  fz2 = dt / (2.0 * g.dx[2]);
     const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
     const unsigned wo = ws.off(xc, yc);  // own column in the workspace
+    // mass-flux export: field f of face (x, y, z)
+    const long long mfE = EX ? mf_stride(n0, n1, n2) : 0;
+    auto mf_put = [&](int f, int z, double v) {
+        mflux[f * mfE + mf_index(n0, n1, x, y, z)] = v;
+    };
+    const bool ex_x = inr(x, -1, n0), ex_y = inr(y, -1, n1);
 
     // plane-to-plane carries (values of the previous plane)
     // (zero until the first plane has been processed; the values derived from
@@ -351,8 +364,18 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         // from the neighbour lane: x in the wavefront, y through LDS) and
         // through the plane's high z-face; their differences over the cell
         const Flux F1zn = hllc(with_ri(qz_hi), with_ri(qz_lo_n), 2, gamma, igm1);
-        const Flux dF1x = next_minus(hllc(prevF(with_ri(qx_hi)), with_ri(qx_lo), 0, gamma, igm1));
-        putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), with_ri(qy_lo), 1, gamma, igm1));
+        const Flux F1x = hllc(prevF(with_ri(qx_hi)), with_ri(qx_lo), 0, gamma, igm1);
+        const Flux dF1x = next_minus(F1x);
+        {
+            const Flux F1y = hllc(getF(ya.v, 0, tD), with_ri(qy_lo), 1, gamma, igm1);
+            putX(yb.v, 0, t, F1y);
+            if (EX) {
+                const bool qw = inr(q, -1, n2);
+                if (hL && rx_f && ex_y && qw) mf_put(0, q, F1x.m);
+                if (hD && ry_f && ex_x && qw) mf_put(1, q, F1y.m);
+                if (inr(q + 1, 0, n2) && ex_x && ex_y) mf_put(2, q + 1, F1zn.m);
+            }
+        }
         // (the round-1 z-flux carried from the plane below is never used
         // before the first plane's)
         const Flux dF1z = fdiff(F1zn, getX(cz, 15, t));
@@ -378,21 +401,29 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             if (fb && hD && hU && rx_fh && ry_c && rz_w) err |= fb;
             Face l = corner_state(qx_lo, dF1y, fy3, gm1, igm1, fb);
             if (fb && hD && hU && rx_f && ry_c && rz_w) err |= fb;
-            dxy = next_minus(hllc(prevF(h), l, 0, gamma, igm1));
+            const Flux Fxy = hllc(prevF(h), l, 0, gamma, igm1);
+            dxy = next_minus(Fxy);
+            if (EX && hL && hD && hU && rx_f && ry_c && rz_w) mf_put(3, q, Fxy.m);
             h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
             if (fb && rx_fh && rz_c && ry_w) err |= fb;
             l = corner_state(qx_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && rx_f && rz_c && ry_w) err |= fb;
-            dxz = next_minus(hllc(prevF(h), l, 0, gamma, igm1));
+            const Flux Fxz = hllc(prevF(h), l, 0, gamma, igm1);
+            dxz = next_minus(Fxz);
+            if (EX && hL && rx_f && rz_c && ex_y) mf_put(4, q, Fxz.m);
         }
         __syncthreads();
         {  // y-families
             Face l = corner_state(qy_lo, dF1x, fx3, gm1, igm1, fb);  // (y|x)
             if (fb && hL && hR && ry_f && rx_c && rz_w) err |= fb;
-            putX(yb.v, 0, t, hllc(getF(ya.v, 0, tD), l, 1, gamma, igm1));
+            const Flux Fyx = hllc(getF(ya.v, 0, tD), l, 1, gamma, igm1);
+            putX(yb.v, 0, t, Fyx);
+            if (EX && hD && hL && hR && ry_f && rx_c && rz_w) mf_put(5, q, Fyx.m);
             l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);  // (y|z)
             if (fb && ry_f && rz_c && rx_w) err |= fb;
-            putX(yb.v, 5, t, hllc(getF(ya.v, 5, tD), l, 1, gamma, igm1));
+            const Flux Fyz = hllc(getF(ya.v, 5, tD), l, 1, gamma, igm1);
+            putX(yb.v, 5, t, Fyz);
+            if (EX && hD && ry_f && rz_c && ex_x) mf_put(6, q, Fyz.m);
         }
         // z-families: the flux through the z-face between q-1 and q
         const bool rz_f = inr(q, 0, n2), rz_fh = inr(q + 1, 0, n2);
@@ -410,6 +441,10 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             h = corner_state(qz_hi, dF1y, fy3, gm1, igm1, fb);
             if (fb && hD && hU && rz_fh && ry_c && rx_w) err |= fb;
             c_zy_hi = h;
+            if (EX && q >= T.z0 && rz_f) {
+                if (hL && hR && rx_c && ex_y) mf_put(7, q, Fzx.m);
+                if (hD && hU && ry_c && ex_x) mf_put(8, q, Fzy.m);
+            }
             // z-differences of the (z|s) fluxes of plane q-1
             dzx = fdiff(Fzx, F2zx);
             dzy = fdiff(Fzy, F2zy);
@@ -426,6 +461,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, igm1, fb);
         if (fb && zin && rz_fh) err |= fb;
         const Flux F3zq = hllc(fz_hi, zl, 2, gamma, igm1);
+        if (EX && zin && q >= T.z0 && rz_f) mf_put(11, q, F3zq.m);
         fz_hi = zh;
         // y-difference of the (y|z) fluxes of plane q (used next plane)
         const Flux dyz = fdiff(getX(yb.v, 5, tU), getX(yb.v, 5, t));
@@ -471,7 +507,9 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         // flux difference over the cell, times dt/dx, right away
         Flux dux;
         {
-            const Flux d = next_minus(hllc(prevF(xh), xl, 0, gamma, igm1));
+            const Flux F3x = hllc(prevF(xh), xl, 0, gamma, igm1);
+            if (EX && pv && hL && hD && hU && rx_f && ry_c && rp_c) mf_put(9, p, F3x.m);
+            const Flux d = next_minus(F3x);
             dux.m = ax * d.m;
             dux.mu = ax * d.mu;
             dux.mv = ax * d.mv;
@@ -480,9 +518,11 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         }
         __syncthreads();
         {
-            Face L = getF_raw(ya.v, 0, tD);
-            L.ri = ya.v[5][tD];
-            putX(yb.v, 0, t, hllc(L, yl, 1, gamma, igm1));
+            Face yd = getF_raw(ya.v, 0, tD);
+            yd.ri = ya.v[5][tD];
+            const Flux F3y = hllc(yd, yl, 1, gamma, igm1);
+            putX(yb.v, 0, t, F3y);
+            if (EX && pv && hD && hL && hR && ry_f && rx_c && rp_c) mf_put(10, p, F3y.m);
         }
         __syncthreads();
         // ---------------------------------------------------- update plane p

@@ -20,7 +20,11 @@
 //                  corrections) + round-2 HLLC, final states (dt/2) +
 //                  round-3 HLLC, conservative update + time-centred gravity
 //                  source + error bits, and the new state's CFL timestep
-//                  (flux_fused.h)
+//                  (flux_fused.h); with species, also the mass flux of every
+//                  Riemann solve
+//   k_sp_*         the species pass: trace, corner, final, update of the
+//                  partial densities of passively advected species, carried
+//                  by those mass fluxes (species.h)
 //
 // Batching: a plan lists, for every stage, a work list of the boxes and the
 // prefix sum of their block counts; a block finds its box by binary search,
@@ -210,6 +214,18 @@ struct Launch {
     unsigned long long *dtn;
     unsigned long long *dtn_min;
 };
+
+// Faces and cells of the index box [-1, n0] x [-1, n1] x [-1, n2] (faces
+// named by the cell above them): the layout of the mass-flux export and of
+// the species pass's arrays.  Each field is padded to 256 bytes.
+__host__ __device__ inline long long mf_stride(int n0, int n1, int n2)
+{
+    return ((long long)(n0 + 2) * (n1 + 2) * (n2 + 2) + 31) / 32 * 32;
+}
+__host__ __device__ inline long long mf_index(int n0, int n1, int x, int y, int z)
+{
+    return ((long long)(z + 1) * (n1 + 2) + (y + 1)) * (n0 + 2) + (x + 1);
+}
 
 struct Box1 {
     Geo g;
@@ -406,6 +422,7 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
 #include "flatten.h"
 #include "flux_fused.h"
 #include "trace_fused.h"
+#include "species.h"
 
 // ---------------------------------------------------------------- host side
 
@@ -508,8 +525,8 @@ Launch single(const Geo &g, const double *U, double *Un, void *ws, const double 
 
 // ---------------------------------------------------------------- profiling hook
 
-enum { PG_FILL, PG_DT, PG_TRACE, PG_FUSED, PG_COUNT };
-const char *const kPgNames[PG_COUNT] = {"fill", "dt", "trace", "flux_update"};
+enum { PG_FILL, PG_DT, PG_TRACE, PG_FUSED, PG_SPECIES, PG_COUNT };
+const char *const kPgNames[PG_COUNT] = {"fill", "dt", "trace", "flux_update", "species"};
 hipEvent_t g_ev[2 * PG_COUNT];
 bool g_ev_on = false;
 
@@ -524,9 +541,10 @@ hydro_status launch_status()
 }
 
 // the whole advance, given a launch template and per-stage grid sizes
+// (mflux: the mass-flux export of a single box for its species pass, or null)
 hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *const *pre,
                              const int *const *order, const hydro_params *prm, int32_t *err32,
-                             hipStream_t st)
+                             hipStream_t st, double *mflux = nullptr)
 {
     int *err_dev = (int *)err32;
     const double gamma = prm->gamma;
@@ -548,8 +566,13 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
     }
     prof(PG_TRACE, 1, st);
     prof(PG_FUSED, 0, st);
-    hipLaunchKernelGGL(k_flux_fused, set(ST_FLUX), dim3(kFT), 0, st, L, gamma, prm->cfl,
-                       prm->grav[0], prm->grav[1], prm->grav[2], err_dev);
+    if (mflux)
+        hipLaunchKernelGGL(k_flux_fused<true>, set(ST_FLUX), dim3(kFT), 0, st, L, gamma,
+                           prm->cfl, prm->grav[0], prm->grav[1], prm->grav[2], err_dev, mflux);
+    else
+        hipLaunchKernelGGL(k_flux_fused<false>, set(ST_FLUX), dim3(kFT), 0, st, L, gamma,
+                           prm->cfl, prm->grav[0], prm->grav[1], prm->grav[2], err_dev,
+                           (double *)nullptr);
     prof(PG_FUSED, 1, st);
     return launch_status();
 }
@@ -731,6 +754,89 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
     Launch L = single(g, U_dev, U_new_dev, ws_dev, dt_dev);
     L.dtn = (unsigned long long *)dt_next_dev;
     return enqueue_advance(L, grid, nullptr, nullptr, prm, err_dev, (hipStream_t)stream);
+}
+
+size_t hydro_species_workspace_bytes(const hydro_box *box, int nspec)
+{
+    if (!box_valid(box) || nspec < 1 || nspec > kMaxSpecies) return 0;
+    const Geo g = make_geo(box);
+    return (size_t)(12 + 15 * nspec) * (size_t)mf_stride(g.n[0], g.n[1], g.n[2]) * sizeof(double);
+}
+
+hydro_status hydro_fill_ghosts_species(double *S_dev, int nspec, const hydro_box *box,
+                                       void *stream)
+{
+    if (!S_dev || nspec < 1 || nspec > kMaxSpecies || !box_valid(box)) return HYDRO_EINVAL;
+    const Geo g = make_geo(box);
+    hipLaunchKernelGGL(k_sp_fill, dim3((unsigned)((g.cs + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, g, S_dev, nspec);
+    return launch_status();
+}
+
+hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const double *S_dev,
+                                 double *S_new_dev, int nspec, const hydro_box *box,
+                                 const hydro_params *prm, const double *dt_dev,
+                                 double *dt_next_dev, void *ws_dev, size_t ws_bytes,
+                                 void *sws_dev, size_t sws_bytes, int32_t *err_dev, void *stream)
+{
+    if (!S_dev || !S_new_dev || !sws_dev || nspec < 1 || nspec > kMaxSpecies ||
+        ((uintptr_t)sws_dev & 255) || !box_valid(box))
+        return HYDRO_EINVAL;
+    const Geo g = make_geo(box);
+    const size_t sbytes = (size_t)nspec * g.cs * sizeof(double);
+    const size_t ubytes = (size_t)5 * g.cs * sizeof(double);
+    // the new species must not overlap the old ones, either gas state or the
+    // species workspace; the workspace must not overlap any array
+    if (overlaps(S_dev, sbytes, S_new_dev, sbytes) || overlaps(S_new_dev, sbytes, U_dev, ubytes) ||
+        overlaps(S_new_dev, sbytes, U_new_dev, ubytes) ||
+        overlaps(sws_dev, sws_bytes, S_dev, sbytes) || overlaps(sws_dev, sws_bytes, S_new_dev, sbytes) ||
+        overlaps(sws_dev, sws_bytes, U_dev, ubytes) || overlaps(sws_dev, sws_bytes, U_new_dev, ubytes) ||
+        (ws_dev && overlaps(sws_dev, sws_bytes, ws_dev, ws_bytes)))
+        return HYDRO_EINVAL;
+    if (sws_bytes < hydro_species_workspace_bytes(box, nspec)) return HYDRO_ENOWS;
+    // the gas step, with the flux kernel exporting its mass fluxes
+    if (!U_dev || !U_new_dev || !dt_dev || !ws_dev || !err_dev || !params_valid(prm) ||
+        !flatten_ok(prm, box, 1))
+        return HYDRO_EINVAL;
+    if (dt_next_dev && overlaps(dt_next_dev, sizeof(double), dt_dev, sizeof(double)))
+        return HYDRO_EINVAL;
+    if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
+    if (overlaps(U_dev, ubytes, U_new_dev, ubytes)) return HYDRO_EINVAL;
+    if (ws_bytes < box_ws_bytes(g)) return HYDRO_ENOWS;
+    const hipStream_t st = (hipStream_t)stream;
+    long long grid[ST_COUNT];
+    for (int s = 0; s < ST_COUNT; ++s) grid[s] = stage_blocks(g, s);
+    Launch L = single(g, U_dev, U_new_dev, ws_dev, dt_dev);
+    L.dtn = (unsigned long long *)dt_next_dev;
+    double *mf = (double *)sws_dev;
+    hydro_status rc = enqueue_advance(L, grid, nullptr, nullptr, prm, err_dev, st, mf);
+    if (rc != HYDRO_OK) return rc;
+    // the species pass
+    SpArgs A;
+    A.g = g;
+    A.U = U_dev;
+    A.S = S_dev;
+    A.Sn = S_new_dev;
+    A.ws = (const char *)ws_dev;
+    A.E = mf_stride(g.n[0], g.n[1], g.n[2]);
+    A.mf = mf;
+    A.Xt = mf + 12 * A.E;
+    A.G2 = A.Xt + 6 * nspec * A.E;
+    A.G3 = A.G2 + 6 * nspec * A.E;
+    A.dt = dt_dev;
+    A.ns = nspec;
+    A.flat = prm->flatten;
+    A.gamma = prm->gamma;
+    const long long nE = (long long)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
+    const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
+    const dim3 gE((unsigned)((nE + kBlock - 1) / kBlock)), gV((unsigned)((nv + kBlock - 1) / kBlock));
+    prof(PG_SPECIES, 0, st);
+    hipLaunchKernelGGL(k_sp_trace, gE, dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL(k_sp_corner, gE, dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL(k_sp_final, gE, dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL(k_sp_update, gV, dim3(kBlock), 0, st, A, (int *)err_dev);
+    prof(PG_SPECIES, 1, st);
+    return launch_status();
 }
 
 hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,

@@ -1,0 +1,257 @@
+// species.h -- passively advected species: ns mass fractions X_s carried by
+// the gas, stored as partial densities rho X_s (their own array, the state
+// layout, ns components).
+//
+// A species moves with the gas: through every face its flux is the mass
+// flux of the same Riemann solve times the mass fraction of the side the
+// mass comes from (the face state on the side the flux leaves; the low side
+// when the flux is zero).  So the species pass needs, from the hydro step,
+// the traced densities (the trace kernel's workspace) and the mass fluxes
+// of all twelve solve families (exported by the flux kernel), and repeats
+// the three rounds of the unsplit step for X alone:
+//   k_sp_trace   X = rho X / rho; each cell's limited parabola of X along
+//                each axis (flattened like the gas), averaged toward each
+//                face like a transverse velocity: over the contact wave when
+//                it moves toward the face, else over the outermost wave;
+//   k_sp_corner  corner-coupled X of each traced state: the corrected
+//                partial density over the corrected density, both
+//                corrected by dt/3 of the round-1 flux difference across the
+//                cell along one transverse axis (the traced X where that
+//                density is not positive); the round-2 species fluxes;
+//   k_sp_final   final X (dt/2 of both round-2 transverse differences);
+//                the round-3 species fluxes;
+//   k_sp_update  the conservative update of rho X.
+// One thread per cell or face of the index box [-1, n] per axis (faces
+// named by the cell above); every stage reads its inputs from HBM.
+#pragma once
+
+namespace {
+
+constexpr int kMaxSpecies = 8;
+
+// Species-pass arrays (doubles, each field mf_stride long, in order):
+// 12 mass-flux fields | traced X: 6 ns (axis, high/low, species) |
+// round-2 species fluxes: 6 ns (family, species) | round-3: 3 ns
+struct SpArgs {
+    Geo g;
+    const double *U;    // gas state (ghosts filled)
+    const double *S;    // partial densities (ghosts filled)
+    double *Sn;         // new partial densities (valid cells written)
+    const char *ws;     // the hydro workspace (traced states, flattening)
+    const double *mf;   // mass-flux export
+    double *Xt, *G2, *G3;
+    const double *dt;
+    int ns;
+    int flat;           // flattening coefficients present in the workspace
+    long long E;        // field stride (doubles)
+    double gamma;
+};
+
+__device__ __forceinline__ bool sp_decode(const SpArgs &A, long long t, int &x, int &y, int &z)
+{
+    const int e0 = A.g.n[0] + 2, e1 = A.g.n[1] + 2, e2 = A.g.n[2] + 2;
+    if (t >= (long long)e0 * e1 * e2) return false;
+    x = (int)(t % e0) - 1;
+    t /= e0;
+    y = (int)(t % e1) - 1;
+    z = (int)(t / e1) - 1;
+    return true;
+}
+
+__device__ __forceinline__ long long sp_idx(const SpArgs &A, int x, int y, int z)
+{
+    return mf_index(A.g.n[0], A.g.n[1], x, y, z);
+}
+
+// traced density of cell (x, y, z) along axis d: high face (side 0) or low
+// face (side 1), from the hydro workspace
+__device__ __forceinline__ double sp_rho_traced(const SpArgs &A, int d, int side, int x, int y,
+                                                int z)
+{
+    WS w;
+    w.base = const_cast<char *>(A.ws);
+    w.pitch = ws_pitch(A.g.n[0], A.g.n[1]);
+    w.nxb = ws_xblocks(A.g.n[0]);
+    return ws_ld(w.plane(z), w.off(x, y), side ? QLO(d, 0) : QHI(d, 0));
+}
+
+// the (t|s) family index: (x|y) (x|z) (y|x) (y|z) (z|x) (z|y)
+__host__ __device__ constexpr int sp_fam(int t, int s) { return 2 * t + (s > t ? s - 1 : s); }
+
+__global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A)
+{
+    int x, y, z;
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (!sp_decode(A, t, x, y, z)) return;
+    const Geo &g = A.g;
+    const double gm1 = A.gamma - 1.0;
+    const long long c = cell(g, x, y, z);
+    const Prim q = prim_of(A.U[c], A.U[g.cs + c], A.U[2 * g.cs + c], A.U[3 * g.cs + c],
+                           A.U[4 * g.cs + c], gm1);
+    const double cs = sound_ri(A.gamma, q.p, q.ri);
+    double f = 1.0;
+    if (A.flat)
+        f = ((const double *)(A.ws + ws_flat_off(g.n[0], g.n[1], g.n[2])))[t];
+    const double dt = *A.dt;
+    const long long stride[3] = {1, (long long)g.s[0], (long long)g.s[0] * g.s[1]};
+    for (int d = 0; d < 3; ++d) {
+        const double un = vel(q, d);
+        const double dtdx = dt / g.dx[d];
+        for (int s = 0; s < A.ns; ++s) {
+            double a[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                const long long cm = c + (m - 2) * stride[d];
+                a[m] = A.S[s * g.cs + cm] / A.U[cm];
+            }
+            const Parab P = ppm(a[0], a[1], a[2], a[3], a[4], f);
+            A.Xt[((d * 2 + 0) * A.ns + s) * A.E + t] = int_hi(P, un > 0.0 ? un : un + cs, dtdx);
+            A.Xt[((d * 2 + 1) * A.ns + s) * A.E + t] = int_lo(P, un < 0.0 ? un : un - cs, dtdx);
+        }
+    }
+}
+
+// round-1 species flux of species s through the d-face named by cell p
+__device__ __forceinline__ double sp_g1(const SpArgs &A, int d, int s, const int (&p)[3])
+{
+    const double F = A.mf[d * A.E + sp_idx(A, p[0], p[1], p[2])];
+    if (F >= 0.0) {
+        int l[3] = {p[0], p[1], p[2]};
+        l[d] -= 1;
+        return F * A.Xt[((d * 2 + 0) * A.ns + s) * A.E + sp_idx(A, l[0], l[1], l[2])];
+    }
+    return F * A.Xt[((d * 2 + 1) * A.ns + s) * A.E + sp_idx(A, p[0], p[1], p[2])];
+}
+
+__global__ void __launch_bounds__(kBlock) k_sp_corner(SpArgs A)
+{
+    int p[3];
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (!sp_decode(A, t, p[0], p[1], p[2])) return;
+    const int *n = A.g.n;
+    const double dt = *A.dt;
+    for (int td = 0; td < 3; ++td)
+        for (int sd = 0; sd < 3; ++sd) {
+            if (sd == td) continue;
+            const int od = 3 - td - sd;
+            // faces of the (td|sd) family: td in [0, n], sd in [0, n), the
+            // third axis in [-1, n]
+            if (p[td] < 0 || p[sd] < 0 || p[sd] >= n[sd]) continue;
+            (void)od;
+            const double fac = dt / (3.0 * A.g.dx[sd]);
+            double xc[2][kMaxSpecies];
+            for (int side = 0; side < 2; ++side) {
+                int c[3] = {p[0], p[1], p[2]};
+                if (!side) c[td] -= 1;
+                int cu[3] = {c[0], c[1], c[2]};
+                cu[sd] += 1;
+                const double rq = sp_rho_traced(A, td, side, c[0], c[1], c[2]);
+                const double den = rq - fac * (A.mf[sd * A.E + sp_idx(A, cu[0], cu[1], cu[2])] -
+                                               A.mf[sd * A.E + sp_idx(A, c[0], c[1], c[2])]);
+                const long long ic = sp_idx(A, c[0], c[1], c[2]);
+                for (int s = 0; s < A.ns; ++s) {
+                    const double xq = A.Xt[((td * 2 + side) * A.ns + s) * A.E + ic];
+                    const double num = rq * xq - fac * (sp_g1(A, sd, s, cu) - sp_g1(A, sd, s, c));
+                    xc[side][s] = den > 0.0 ? num / den : xq;
+                }
+            }
+            const int fam = sp_fam(td, sd);
+            const double F = A.mf[(3 + fam) * A.E + t];
+            for (int s = 0; s < A.ns; ++s)
+                A.G2[(fam * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xc[0][s] : xc[1][s]);
+        }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sp_final(SpArgs A)
+{
+    int p[3];
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (!sp_decode(A, t, p[0], p[1], p[2])) return;
+    const int *n = A.g.n;
+    const double dt = *A.dt;
+    for (int d = 0; d < 3; ++d) {
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        // faces: d in [0, n], the transverse axes in [0, n)
+        if (p[d] < 0 || p[t1] < 0 || p[t1] >= n[t1] || p[t2] < 0 || p[t2] >= n[t2]) continue;
+        const double f1 = dt / (2.0 * A.g.dx[t1]);
+        const double f2 = dt / (2.0 * A.g.dx[t2]);
+        const int fa = sp_fam(t1, t2), fb = sp_fam(t2, t1);
+        double xf[2][kMaxSpecies];
+        for (int side = 0; side < 2; ++side) {
+            int c[3] = {p[0], p[1], p[2]};
+            if (!side) c[d] -= 1;
+            int c1[3] = {c[0], c[1], c[2]}, c2[3] = {c[0], c[1], c[2]};
+            c1[t1] += 1;
+            c2[t2] += 1;
+            const long long ic = sp_idx(A, c[0], c[1], c[2]);
+            const long long i1 = sp_idx(A, c1[0], c1[1], c1[2]);
+            const long long i2 = sp_idx(A, c2[0], c2[1], c2[2]);
+            const double rq = sp_rho_traced(A, d, side, c[0], c[1], c[2]);
+            const double den = (rq - f1 * (A.mf[(3 + fa) * A.E + i1] - A.mf[(3 + fa) * A.E + ic])) -
+                               f2 * (A.mf[(3 + fb) * A.E + i2] - A.mf[(3 + fb) * A.E + ic]);
+            for (int s = 0; s < A.ns; ++s) {
+                const double xq = A.Xt[((d * 2 + side) * A.ns + s) * A.E + ic];
+                const double *GA = A.G2 + (fa * A.ns + s) * A.E;
+                const double *GB = A.G2 + (fb * A.ns + s) * A.E;
+                const double num = (rq * xq - f1 * (GA[i1] - GA[ic])) - f2 * (GB[i2] - GB[ic]);
+                xf[side][s] = den > 0.0 ? num / den : xq;
+            }
+        }
+        const double F = A.mf[(9 + d) * A.E + t];
+        for (int s = 0; s < A.ns; ++s)
+            A.G3[(d * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xf[0][s] : xf[1][s]);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sp_update(SpArgs A, int *err_dev)
+{
+    const Geo &g = A.g;
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
+    if (t >= nv) return;
+    const int x = (int)(t % g.n[0]);
+    t /= g.n[0];
+    const int y = (int)(t % g.n[1]);
+    const int z = (int)(t / g.n[1]);
+    const double dt = *A.dt;
+    const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
+    const long long i0 = sp_idx(A, x, y, z);
+    const long long ix = sp_idx(A, x + 1, y, z), iy = sp_idx(A, x, y + 1, z),
+                    iz = sp_idx(A, x, y, z + 1);
+    const long long c = cell(g, x, y, z);
+    int err = 0;
+    for (int s = 0; s < A.ns; ++s) {
+        const double *Gx = A.G3 + (0 * A.ns + s) * A.E;
+        const double *Gy = A.G3 + (1 * A.ns + s) * A.E;
+        const double *Gz = A.G3 + (2 * A.ns + s) * A.E;
+        double du = ax * (Gx[ix] - Gx[i0]);
+        du = du + ay * (Gy[iy] - Gy[i0]);
+        du = du + az * (Gz[iz] - Gz[i0]);
+        const double v = A.S[s * g.cs + c] - du;
+        if (!isfinite(v)) err |= HYDRO_ERR_NONFINITE;
+        A.Sn[s * g.cs + c] = v;
+    }
+    if (err) atomicOr(err_dev, err);
+}
+
+// ghost cells of the species array: the gas's boundary rules without any
+// sign flip (each ghost cell copies the cell its per-axis mapping names)
+__global__ void __launch_bounds__(kBlock) k_sp_fill(Geo g, double *S, int ns)
+{
+    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g.cs) return;
+    const int i = (int)(t % g.s[0]) - g.ng;
+    const long long r = t / g.s[0];
+    const int j = (int)(r % g.s[1]) - g.ng;
+    const int k = (int)(r / g.s[1]) - g.ng;
+    const bool gi = i < 0 || i >= g.n[0], gj = j < 0 || j >= g.n[1], gk = k < 0 || k >= g.n[2];
+    if (!gi && !gj && !gk) return;
+    int flip;
+    const int si = gi ? ghost_src(i, g.n[0], g.bc_lo[0], g.bc_hi[0], flip) : i;
+    const int sj = gj ? ghost_src(j, g.n[1], g.bc_lo[1], g.bc_hi[1], flip) : j;
+    const int sk = gk ? ghost_src(k, g.n[2], g.bc_lo[2], g.bc_hi[2], flip) : k;
+    const long long src = cell(g, si, sj, sk);
+    for (int s = 0; s < ns; ++s) S[s * g.cs + t] = S[s * g.cs + src];
+}
+
+}  // namespace

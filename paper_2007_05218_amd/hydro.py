@@ -25,7 +25,8 @@ EXPORTS = ("hydro_state_elems", "hydro_workspace_bytes", "hydro_fill_ghosts", "e
            "advance_box", "estimate_dt_boxes", "advance_boxes", "hydro_plan_create",
            "hydro_plan_destroy", "hydro_status_string", "hydro_stage_count",
            "hydro_stage_name", "hydro_set_stage_events", "hydro_fill_ghosts_boxes",
-           "hydro_level_create", "hydro_level_destroy", "hydro_fill_ghosts_level")
+           "hydro_level_create", "hydro_level_destroy", "hydro_fill_ghosts_level",
+           "hydro_species_workspace_bytes", "hydro_fill_ghosts_species", "advance_box_species")
 
 
 class HydroBox(C.Structure):
@@ -86,9 +87,15 @@ def lib():
         L.hydro_level_destroy.argtypes = [vp]
         L.hydro_level_destroy.restype = None
         L.hydro_fill_ghosts_level.argtypes = [C.c_int, vp, vp, vp]
+        L.hydro_species_workspace_bytes.argtypes = [bp, C.c_int]
+        L.hydro_species_workspace_bytes.restype = C.c_size_t
+        L.hydro_fill_ghosts_species.argtypes = [vp, C.c_int, bp, vp]
+        L.advance_box_species.argtypes = [vp, vp, vp, vp, C.c_int, bp, pp, vp, vp, vp,
+                                          C.c_size_t, vp, C.c_size_t, vp, vp]
         for f in ("hydro_fill_ghosts", "estimate_dt", "advance_box", "estimate_dt_boxes",
                   "advance_boxes", "hydro_plan_create", "hydro_fill_ghosts_boxes",
-                  "hydro_level_create", "hydro_fill_ghosts_level"):
+                  "hydro_level_create", "hydro_fill_ghosts_level", "hydro_fill_ghosts_species",
+                  "advance_box_species"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -212,6 +219,70 @@ class Box:
     def state(self):
         """Host copy of the current state (ghosts as last filled)."""
         return self.U.cpu().numpy()
+
+
+# ---- passively advected species: S is a CUDA float64 tensor of shape
+# (nspec,) + the state's spatial shape holding the partial densities rho X_s
+
+def species_workspace_bytes(box, nspec):
+    return int(lib().hydro_species_workspace_bytes(C.byref(make_box(box)), int(nspec)))
+
+
+def _check_species(S, box):
+    per = state_elems(box) // 5
+    if S.numel() % per or not 1 <= S.numel() // per:
+        raise ValueError("species tensor of %d elements does not fit the box" % S.numel())
+    return S.numel() // per
+
+
+def fill_ghosts_species(S, box, stream=None):
+    ns = _check_species(S, box)
+    _check("hydro_fill_ghosts_species", lib().hydro_fill_ghosts_species(
+        _ptr(S), ns, C.byref(make_box(box)), _stream(stream)))
+
+
+def advance_box_species(U, Unew, S, Snew, box, prm, dt, ws, sws, err, stream=None,
+                        dt_next=None):
+    """advance_box plus the species: Snew's valid cells from S (ghosts filled)."""
+    _check_state(U, box)
+    _check_state(Unew, box)
+    ns = _check_species(S, box)
+    if _check_species(Snew, box) != ns:
+        raise ValueError("S and Snew differ in species count")
+    _check("advance_box_species", lib().advance_box_species(
+        _ptr(U), _ptr(Unew), _ptr(S), _ptr(Snew), ns, C.byref(make_box(box)),
+        C.byref(make_params(prm)), _ptr(dt), _ptr(dt_next) if dt_next is not None else None,
+        _ptr(ws, torch.uint8), ws.numel(), _ptr(sws, torch.uint8), sws.numel(),
+        _ptr(err, torch.int32), _stream(stream)))
+
+
+class SpeciesBox(Box):
+    """A Box that also carries nspec passively advected species (partial
+    densities S, host array of shape (nspec,) + the state's spatial shape)."""
+
+    def __init__(self, U_host, S_host, box, prm, device="cuda"):
+        super().__init__(U_host, box, prm, device)
+        self.S = torch.as_tensor(S_host, dtype=torch.float64).to(device).contiguous()
+        self.Snew = torch.empty_like(self.S)
+        self.sws = torch.empty(max(species_workspace_bytes(self.box, self.S.shape[0]), 256),
+                               dtype=torch.uint8, device=device)
+
+    def step(self, stream=None):
+        if self.have_dt:
+            fill_ghosts(self.U, self.box, stream)
+            self.dt, self.dt_next = self.dt_next, self.dt
+        else:
+            estimate_dt(self.U, self.box, self.prm, self.dt, stream)
+        fill_ghosts_species(self.S, self.box, stream)
+        advance_box_species(self.U, self.Unew, self.S, self.Snew, self.box, self.prm, self.dt,
+                            self.ws, self.sws, self.err, stream, dt_next=self.dt_next)
+        self.U, self.Unew = self.Unew, self.U
+        self.S, self.Snew = self.Snew, self.S
+        self.have_dt = True
+
+    def species(self):
+        """Host copy of the current partial densities."""
+        return self.S.cpu().numpy()
 
 
 class Plan:

@@ -184,3 +184,36 @@ def test_level_rejects_bad_tilings(bad):
     assert h.value is None
     # a null handle and a mismatched box count are refused by the fill
     assert L.hydro_fill_ghosts_level(1, C.c_void_p(8), None, None) == hydro.HYDRO_EINVAL
+
+
+def test_species_sizes_and_rejections():
+    d = inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1))
+    assert hydro.species_workspace_bytes(d, 0) == 0
+    assert hydro.species_workspace_bytes(d, 9) == 0
+    # twelve mass-flux fields and 15 per species (traced values, round-2 and
+    # round-3 species fluxes) over the 10^3 index box, each padded to 256 B
+    field = -(-10 ** 3 // 32) * 32 * 8
+    assert hydro.species_workspace_bytes(d, 1) == 27 * field
+    assert hydro.species_workspace_bytes(d, 3) == 57 * field
+    L = hydro.lib()
+    b = hydro.make_box(d)
+    p = hydro.make_params(inputs.params_desc())
+    a = C.c_void_p(1 << 30)
+    ws = C.c_void_p(1 << 34)
+    nws = hydro.workspace_bytes(d)
+    S, Sn, sws = C.c_void_p(1 << 38), C.c_void_p(1 << 39), C.c_void_p(1 << 40)
+    nsws = hydro.species_workspace_bytes(d, 2)
+
+    def call(S_, Sn_, ns, sws_, nb, U=a, Un=C.c_void_p(1 << 32)):
+        return L.advance_box_species(U, Un, S_, Sn_, ns, C.byref(b), C.byref(p), a, None, ws, nws,
+                                     sws_, nb, a, None)
+    assert call(None, Sn, 2, sws, nsws) == hydro.HYDRO_EINVAL
+    assert call(S, Sn, 0, sws, nsws) == hydro.HYDRO_EINVAL
+    assert call(S, Sn, 9, sws, nsws) == hydro.HYDRO_EINVAL
+    assert call(S, C.c_void_p((1 << 38) + 8), 2, sws, nsws) == hydro.HYDRO_EINVAL   # S overlap
+    assert call(S, Sn, 2, C.c_void_p((1 << 40) + 8), nsws) == hydro.HYDRO_EINVAL    # misaligned
+    assert call(S, Sn, 2, C.c_void_p(1 << 38), nsws) == hydro.HYDRO_EINVAL          # sws over S
+    assert call(S, Sn, 2, sws, nsws - 256) == hydro.HYDRO_ENOWS
+    assert call(S, Sn, 2, sws, nsws, Un=C.c_void_p((1 << 30) + 8)) == hydro.HYDRO_EINVAL
+    assert L.hydro_fill_ghosts_species(None, 2, C.byref(b), None) == hydro.HYDRO_EINVAL
+    assert L.hydro_fill_ghosts_species(S, 9, C.byref(b), None) == hydro.HYDRO_EINVAL
