@@ -16,7 +16,8 @@ Also reported on the same JSON line:
                 against the FP64 VALU issue peak of the chip
   cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
                 same workload (rank 0, N = 1 only)
-  also          secondary workloads: the 256^3 Kelvin-Helmholtz box; the
+  also          secondary workloads: the 256^3 Kelvin-Helmholtz box, also
+                with two passively advected species; the
                 paper's Sedov blast at its per-node size (256^3 as 64 boxes of
                 64^3 tiling the domain, with the ghost exchange between boxes,
                 and as one box); the 512-box batched level (one launch per
@@ -45,7 +46,7 @@ HBM_PEAK = 8.0e12
 KERNEL_STAGES = {"trace": ["prim", "trace"],
                  "flux_update": ["flux1", "corner_flux2", "final_flux3", "update"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rt512_traffic.json")
-KERNEL_SYMBOL = {"trace": "k_trace_fused<false>", "flux_update": "k_flux_fused"}
+KERNEL_SYMBOL = {"trace": "k_trace_fused<false>", "flux_update": "k_flux_fused<false>"}
 
 
 # the sources the profiled step kernels are built from
@@ -86,7 +87,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workloads", default="rt512,kh256,sedov,level,serve",
+    ap.add_argument("--workloads", default="rt512,kh256,species,sedov,level,serve",
                     help="comma list of rt512, kh256, sedov, level, serve, copy (a plain 2 GiB "
                          "device copy, the reference for HBM traffic counters)")
     ap.add_argument("--serve-requests", type=int, default=120)
@@ -97,8 +98,8 @@ def parse():
     return ap.parse_args()
 
 
-def time_box(hydro, torch, U, box, prm, steps, warmup):
-    B = hydro.Box(U, box, prm)
+def time_box(hydro, torch, U, box, prm, steps, warmup, B=None):
+    B = B if B is not None else hydro.Box(U, box, prm)
     for _ in range(warmup):
         B.step()
     torch.cuda.synchronize()
@@ -120,6 +121,32 @@ def time_box(hydro, torch, U, box, prm, steps, warmup):
     del B
     torch.cuda.empty_cache()
     return ms, wall, timer, err
+
+
+def time_species(hydro, torch, inputs, steps, warmup, ns=2, n=256):
+    """KH n^3 with ns passively advected species (advance_box_species) against
+    the same box without them; the species pass's time and its array traffic
+    (each of its arrays written once and read back once, the partial
+    densities read and written once) as a bandwidth."""
+    U, box, prm = inputs.kh(n, seed=1)
+    S = inputs.species(U, box, ns, seed=3)
+    B = hydro.SpeciesBox(U, S, box, prm)
+    ms, _, timer, err = time_box(hydro, torch, None, box, prm, steps, warmup, B=B)
+    del B
+    torch.cuda.empty_cache()
+    ms0, _, _, _ = time_box(hydro, torch, U, box, prm, steps, warmup)
+    ncell = n ** 3
+    st = {k: v / max(timer.calls, 1) for k, v in timer.total_ms.items()}
+    sp_ms = st.get("species", 0.0)
+    e = (n + 2) ** 3
+    pass_bytes = 2 * (12 + 15 * ns) * 8 * e + 2 * 8 * ns * ncell
+    return {"species": ns, "cu_per_s": ncell * steps / (ms * 1e-3),
+            "ms_per_step": ms / steps, "ms_per_step_without_species": ms0 / steps,
+            "stage_ms": {k: round(v, 3) for k, v in st.items()},
+            "species_pass_ms": sp_ms,
+            "species_pass_array_GB": pass_bytes / 1e9,
+            "species_pass_GBps": pass_bytes / (sp_ms * 1e-3) / 1e9 if sp_ms > 0 else None,
+            "err": err}
 
 
 def _time_level_once(hydro, torch, states, boxes, prm, steps, warmup, table=None):
@@ -471,6 +498,10 @@ def main():
         also["kh256"] = {"cu_per_s": n2 * args.steps / (ms2 * 1e-3),
                          "ms_per_step": ms2 / args.steps, "err": e2}
         del U2
+    if "species" in work:
+        log("timing KH 256^3 with 2 passively advected species")
+        also["kh256_species2"] = time_species(hydro, torch, inputs, args.steps, args.warmup)
+        log("species:", json.dumps(also["kh256_species2"]))
     if "sedov" in work:
         log("timing the Sedov blast, 256^3 as 64 boxes of 64^3 and as one box")
         also["sedov256"] = time_sedov(hydro, torch, inputs, args.steps, args.warmup)

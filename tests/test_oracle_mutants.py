@@ -62,8 +62,8 @@ MUTANTS = {
         "double az = lam[1] > 0.0 ? drz - dpz * ics2 : 0.0;",
         "double az = lam[1] > 0.0 ? drz + dpz * ics2 : 0.0;"),
     "corner coupling factor dt/2 for dt/3": (
-        "const double fac = dt / (3.0 * b->dx[sd]);",
-        "const double fac = dt / (2.0 * b->dx[sd]);"),
+        "goto done; }\n            const double fac = dt / (3.0 * b->dx[sd]);",
+        "goto done; }\n            const double fac = dt / (2.0 * b->dx[sd]);"),
     "flattening reaches toward the higher pressure": (
         "int s = p7[4] > p7[2] ? -1 : 1;",
         "int s = p7[4] > p7[2] ? 1 : -1;"),
