@@ -832,8 +832,8 @@ hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const d
     const dim3 gE((unsigned)((nE + kBlock - 1) / kBlock)), gV((unsigned)((nv + kBlock - 1) / kBlock));
     prof(PG_SPECIES, 0, st);
     hipLaunchKernelGGL(k_sp_trace, gE, dim3(kBlock), 0, st, A);
-    hipLaunchKernelGGL(k_sp_corner, gE, dim3(kBlock), 0, st, A);
-    hipLaunchKernelGGL(k_sp_final, gE, dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL(k_sp_corner, dim3(sp_part_blocks(nE, 6)), dim3(kBlock), 0, st, A);
+    hipLaunchKernelGGL(k_sp_final, dim3(sp_part_blocks(nE, 3)), dim3(kBlock), 0, st, A);
     hipLaunchKernelGGL(k_sp_update, gV, dim3(kBlock), 0, st, A, (int *)err_dev);
     prof(PG_SPECIES, 1, st);
     return launch_status();

@@ -75,7 +75,25 @@ __device__ __forceinline__ double sp_rho_traced(const SpArgs &A, int d, int side
     return ws_ld(w.plane(z), w.off(x, y), side ? QLO(d, 0) : QHI(d, 0));
 }
 
-// the (t|s) family index: (x|y) (x|z) (y|x) (y|z) (z|x) (z|y)
+// Block b of a stage with nf parts per face (flux families or axes): part
+// (b / 8) % nf of cell block ((b / 8) / nf) * 8 + b % 8.  Blocks are dealt to
+// the 8 XCDs round-robin (b % 8), so the nf parts of one cell block run on
+// one XCD, close in time, and share what they read in its L2.
+__device__ __forceinline__ long long sp_part(int nf, int &part)
+{
+    const long long b = blockIdx.x;
+    const long long r = b / 8;
+    part = (int)(r % nf);
+    return ((r / nf) * 8 + b % 8) * kBlock + threadIdx.x;
+}
+__host__ inline unsigned sp_part_blocks(long long items, int nf)
+{
+    const long long nb = (items + kBlock - 1) / kBlock;
+    return (unsigned)((nb + 7) / 8 * 8 * nf);
+}
+
+// the (t|s) family index: (x|y) (x|z) (y|x) (y|z) (z|x) (z|y); the corner
+// stage inverts it as t = fam / 2, s = fam % 2 (+1 when >= t)
 __host__ __device__ constexpr int sp_fam(int t, int s) { return 2 * t + (s > t ? s - 1 : s); }
 
 __global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A)
@@ -111,95 +129,104 @@ __global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A)
     }
 }
 
-// round-1 species flux of species s through the d-face named by cell p
-__device__ __forceinline__ double sp_g1(const SpArgs &A, int d, int s, const int (&p)[3])
-{
-    const double F = A.mf[d * A.E + sp_idx(A, p[0], p[1], p[2])];
-    if (F >= 0.0) {
-        int l[3] = {p[0], p[1], p[2]};
-        l[d] -= 1;
-        return F * A.Xt[((d * 2 + 0) * A.ns + s) * A.E + sp_idx(A, l[0], l[1], l[2])];
-    }
-    return F * A.Xt[((d * 2 + 1) * A.ns + s) * A.E + sp_idx(A, p[0], p[1], p[2])];
-}
-
+// Corner stage: one part per (td|sd) family.  Each thread takes one face of
+// the family: both sides' traced X corrected by dt/3 of the round-1 species
+// flux difference across their cell along sd (the round-1 species flux
+// through an sd-face is its mass flux times the traced X of the side the
+// mass leaves), then the round-2 species flux through the face.
 __global__ void __launch_bounds__(kBlock) k_sp_corner(SpArgs A)
 {
-    int p[3];
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    int p[3], fam;
+    const long long t = sp_part(6, fam);
     if (!sp_decode(A, t, p[0], p[1], p[2])) return;
+    const int td = fam / 2, sd = (fam % 2) < td ? (fam % 2) : (fam % 2) + 1;
     const int *n = A.g.n;
-    const double dt = *A.dt;
-    for (int td = 0; td < 3; ++td)
-        for (int sd = 0; sd < 3; ++sd) {
-            if (sd == td) continue;
-            const int od = 3 - td - sd;
-            // faces of the (td|sd) family: td in [0, n], sd in [0, n), the
-            // third axis in [-1, n]
-            if (p[td] < 0 || p[sd] < 0 || p[sd] >= n[sd]) continue;
-            (void)od;
-            const double fac = dt / (3.0 * A.g.dx[sd]);
-            double xc[2][kMaxSpecies];
-            for (int side = 0; side < 2; ++side) {
-                int c[3] = {p[0], p[1], p[2]};
-                if (!side) c[td] -= 1;
-                int cu[3] = {c[0], c[1], c[2]};
-                cu[sd] += 1;
-                const double rq = sp_rho_traced(A, td, side, c[0], c[1], c[2]);
-                const double den = rq - fac * (A.mf[sd * A.E + sp_idx(A, cu[0], cu[1], cu[2])] -
-                                               A.mf[sd * A.E + sp_idx(A, c[0], c[1], c[2])]);
-                const long long ic = sp_idx(A, c[0], c[1], c[2]);
-                for (int s = 0; s < A.ns; ++s) {
-                    const double xq = A.Xt[((td * 2 + side) * A.ns + s) * A.E + ic];
-                    const double num = rq * xq - fac * (sp_g1(A, sd, s, cu) - sp_g1(A, sd, s, c));
-                    xc[side][s] = den > 0.0 ? num / den : xq;
-                }
-            }
-            const int fam = sp_fam(td, sd);
-            const double F = A.mf[(3 + fam) * A.E + t];
-            for (int s = 0; s < A.ns; ++s)
-                A.G2[(fam * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xc[0][s] : xc[1][s]);
+    // faces of the family: td in [0, n], sd in [0, n), the third axis in [-1, n]
+    if (p[td] < 0 || p[sd] < 0 || p[sd] >= n[sd]) return;
+    const double fac = *A.dt / (3.0 * A.g.dx[sd]);
+    const double *F1 = A.mf + sd * A.E;
+    long long ic[2], iu[2], il[2];  // the side's cell, its sd-neighbours above and below
+    double Fl[2], Fh[2], rq[2], den[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        int c[3] = {p[0], p[1], p[2]};
+        if (!side) c[td] -= 1;
+        ic[side] = sp_idx(A, c[0], c[1], c[2]);
+        c[sd] += 1;
+        iu[side] = sp_idx(A, c[0], c[1], c[2]);
+        c[sd] -= 2;
+        il[side] = sp_idx(A, c[0], c[1], c[2]);
+        c[sd] += 1;
+        Fl[side] = F1[ic[side]];
+        Fh[side] = F1[iu[side]];
+        rq[side] = sp_rho_traced(A, td, side, c[0], c[1], c[2]);
+        den[side] = rq[side] - fac * (Fh[side] - Fl[side]);
+    }
+    const double F = A.mf[(3 + fam) * A.E + t];
+    for (int s = 0; s < A.ns; ++s) {
+        const double *Xq0 = A.Xt + ((td * 2 + 0) * A.ns + s) * A.E;
+        const double *Xq1 = A.Xt + ((td * 2 + 1) * A.ns + s) * A.E;
+        const double *Xh = A.Xt + ((sd * 2 + 0) * A.ns + s) * A.E;
+        const double *Xl = A.Xt + ((sd * 2 + 1) * A.ns + s) * A.E;
+        double xs[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const double xq = (side ? Xq1 : Xq0)[ic[side]];
+            const double gh = Fh[side] * (Fh[side] >= 0.0 ? Xh[ic[side]] : Xl[iu[side]]);
+            const double gl = Fl[side] * (Fl[side] >= 0.0 ? Xh[il[side]] : Xl[ic[side]]);
+            const double num = rq[side] * xq - fac * (gh - gl);
+            xs[side] = den[side] > 0.0 ? num / den[side] : xq;
         }
+        A.G2[(fam * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xs[0] : xs[1]);
+    }
 }
 
+// Final stage: one part per axis d.  Each thread takes one d-face: both
+// sides' traced X corrected by dt/2 of the two round-2 transverse species
+// flux differences, then the round-3 species flux through the face.
 __global__ void __launch_bounds__(kBlock) k_sp_final(SpArgs A)
 {
-    int p[3];
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    int p[3], d;
+    const long long t = sp_part(3, d);
     if (!sp_decode(A, t, p[0], p[1], p[2])) return;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const int *n = A.g.n;
+    // faces: d in [0, n], the transverse axes in [0, n)
+    if (p[d] < 0 || p[t1] < 0 || p[t1] >= n[t1] || p[t2] < 0 || p[t2] >= n[t2]) return;
     const double dt = *A.dt;
-    for (int d = 0; d < 3; ++d) {
-        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        // faces: d in [0, n], the transverse axes in [0, n)
-        if (p[d] < 0 || p[t1] < 0 || p[t1] >= n[t1] || p[t2] < 0 || p[t2] >= n[t2]) continue;
-        const double f1 = dt / (2.0 * A.g.dx[t1]);
-        const double f2 = dt / (2.0 * A.g.dx[t2]);
-        const int fa = sp_fam(t1, t2), fb = sp_fam(t2, t1);
-        double xf[2][kMaxSpecies];
+    const double f1 = dt / (2.0 * A.g.dx[t1]);
+    const double f2 = dt / (2.0 * A.g.dx[t2]);
+    const int fa = sp_fam(t1, t2), fb = sp_fam(t2, t1);
+    long long ic[2], i1[2], i2[2];
+    double rq[2], den[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        int c[3] = {p[0], p[1], p[2]};
+        if (!side) c[d] -= 1;
+        int c1[3] = {c[0], c[1], c[2]}, c2[3] = {c[0], c[1], c[2]};
+        c1[t1] += 1;
+        c2[t2] += 1;
+        ic[side] = sp_idx(A, c[0], c[1], c[2]);
+        i1[side] = sp_idx(A, c1[0], c1[1], c1[2]);
+        i2[side] = sp_idx(A, c2[0], c2[1], c2[2]);
+        rq[side] = sp_rho_traced(A, d, side, c[0], c[1], c[2]);
+        const double *MA = A.mf + (3 + fa) * A.E, *MB = A.mf + (3 + fb) * A.E;
+        den[side] = (rq[side] - f1 * (MA[i1[side]] - MA[ic[side]])) -
+                    f2 * (MB[i2[side]] - MB[ic[side]]);
+    }
+    const double F = A.mf[(9 + d) * A.E + t];
+    for (int s = 0; s < A.ns; ++s) {
+        const double *GA = A.G2 + (fa * A.ns + s) * A.E;
+        const double *GB = A.G2 + (fb * A.ns + s) * A.E;
+        double xs[2];
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
-            int c[3] = {p[0], p[1], p[2]};
-            if (!side) c[d] -= 1;
-            int c1[3] = {c[0], c[1], c[2]}, c2[3] = {c[0], c[1], c[2]};
-            c1[t1] += 1;
-            c2[t2] += 1;
-            const long long ic = sp_idx(A, c[0], c[1], c[2]);
-            const long long i1 = sp_idx(A, c1[0], c1[1], c1[2]);
-            const long long i2 = sp_idx(A, c2[0], c2[1], c2[2]);
-            const double rq = sp_rho_traced(A, d, side, c[0], c[1], c[2]);
-            const double den = (rq - f1 * (A.mf[(3 + fa) * A.E + i1] - A.mf[(3 + fa) * A.E + ic])) -
-                               f2 * (A.mf[(3 + fb) * A.E + i2] - A.mf[(3 + fb) * A.E + ic]);
-            for (int s = 0; s < A.ns; ++s) {
-                const double xq = A.Xt[((d * 2 + side) * A.ns + s) * A.E + ic];
-                const double *GA = A.G2 + (fa * A.ns + s) * A.E;
-                const double *GB = A.G2 + (fb * A.ns + s) * A.E;
-                const double num = (rq * xq - f1 * (GA[i1] - GA[ic])) - f2 * (GB[i2] - GB[ic]);
-                xf[side][s] = den > 0.0 ? num / den : xq;
-            }
+            const double xq = A.Xt[((d * 2 + side) * A.ns + s) * A.E + ic[side]];
+            const double num = (rq[side] * xq - f1 * (GA[i1[side]] - GA[ic[side]])) -
+                               f2 * (GB[i2[side]] - GB[ic[side]]);
+            xs[side] = den[side] > 0.0 ? num / den[side] : xq;
         }
-        const double F = A.mf[(9 + d) * A.E + t];
-        for (int s = 0; s < A.ns; ++s)
-            A.G3[(d * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xf[0][s] : xf[1][s]);
+        A.G3[(d * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xs[0] : xs[1]);
     }
 }
 
