@@ -327,12 +327,29 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
                  fz2 = dt / (2.0 * g.dx[2]);
     const double ax = dt / g.dx[0], ay = dt / g.dx[1], az = dt / g.dx[2];
     const unsigned wo = ws.off(xc, yc);  // own column in the workspace
-    // mass-flux export: field f of face (x, y, z)
+    // mass-flux export: field f of face (x, y, z).  Bit f of exm: the lane
+    // computes field f from valid data and its face lies in the field's
+    // region (the plane's conditions are checked where the flux is formed).
     const long long mfE = EX ? mf_stride(n0, n1, n2) : 0;
+    const long long mfP = (long long)(n0 + 2) * (n1 + 2);
+    // (a uniform plane base plus the lane's 32-bit byte offset, as for the
+    // workspace: (n0+2)(n1+2) doubles fit 32-bit offsets for every valid box)
+    const unsigned mfo = (unsigned)((y + 1) * (n0 + 2) + (x + 1)) * 8u;
     auto mf_put = [&](int f, int z, double v) {
-        mflux[f * mfE + mf_index(n0, n1, x, y, z)] = v;
+        stb64(mflux + f * mfE + (long long)(z + 1) * mfP, mfo, v);
     };
-    const bool ex_x = inr(x, -1, n0), ex_y = inr(y, -1, n1);
+    unsigned exm = 0;
+    if (EX) {
+        const bool ex_x = inr(x, -1, n0), ex_y = inr(y, -1, n1);
+        const bool fx = hL && rx_f, fy = hD && ry_f, cx = hL && hR && rx_c, cy = hD && hU && ry_c;
+        exm = (unsigned)(fx && ex_y) << 0 | (unsigned)(fy && ex_x) << 1 |
+              (unsigned)(ex_x && ex_y) << 2 | (unsigned)(fx && cy) << 3 |
+              (unsigned)(fx && ex_y) << 4 | (unsigned)(fy && cx) << 5 |
+              (unsigned)(fy && ex_x) << 6 | (unsigned)(cx && ex_y) << 7 |
+              (unsigned)(cy && ex_x) << 8 | (unsigned)(fx && cy) << 9 |
+              (unsigned)(fy && cx) << 10 | (unsigned)(cx && cy) << 11;
+    }
+    auto exb = [&](int f) { return EX && ((exm >> f) & 1u); };
 
     // plane-to-plane carries (values of the previous plane)
     // (zero until the first plane has been processed; the values derived from
@@ -364,17 +381,14 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         // from the neighbour lane: x in the wavefront, y through LDS) and
         // through the plane's high z-face; their differences over the cell
         const Flux F1zn = hllc(with_ri(qz_hi), with_ri(qz_lo_n), 2, gamma, igm1);
+        if (exb(2) && inr(q + 1, 0, n2)) mf_put(2, q + 1, F1zn.m);
         const Flux F1x = hllc(prevF(with_ri(qx_hi)), with_ri(qx_lo), 0, gamma, igm1);
+        if (exb(0) && rz_w) mf_put(0, q, F1x.m);
         const Flux dF1x = next_minus(F1x);
         {
             const Flux F1y = hllc(getF(ya.v, 0, tD), with_ri(qy_lo), 1, gamma, igm1);
             putX(yb.v, 0, t, F1y);
-            if (EX) {
-                const bool qw = inr(q, -1, n2);
-                if (hL && rx_f && ex_y && qw) mf_put(0, q, F1x.m);
-                if (hD && ry_f && ex_x && qw) mf_put(1, q, F1y.m);
-                if (inr(q + 1, 0, n2) && ex_x && ex_y) mf_put(2, q + 1, F1zn.m);
-            }
+            if (exb(1) && rz_w) mf_put(1, q, F1y.m);
         }
         // (the round-1 z-flux carried from the plane below is never used
         // before the first plane's)
@@ -403,14 +417,14 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             if (fb && hD && hU && rx_f && ry_c && rz_w) err |= fb;
             const Flux Fxy = hllc(prevF(h), l, 0, gamma, igm1);
             dxy = next_minus(Fxy);
-            if (EX && hL && hD && hU && rx_f && ry_c && rz_w) mf_put(3, q, Fxy.m);
+            if (exb(3) && rz_w) mf_put(3, q, Fxy.m);
             h = corner_state(qx_hi, dF1z, fz3, gm1, igm1, fb);  // (x|z)
             if (fb && rx_fh && rz_c && ry_w) err |= fb;
             l = corner_state(qx_lo, dF1z, fz3, gm1, igm1, fb);
             if (fb && rx_f && rz_c && ry_w) err |= fb;
             const Flux Fxz = hllc(prevF(h), l, 0, gamma, igm1);
             dxz = next_minus(Fxz);
-            if (EX && hL && rx_f && rz_c && ex_y) mf_put(4, q, Fxz.m);
+            if (exb(4) && rz_c) mf_put(4, q, Fxz.m);
         }
         __syncthreads();
         {  // y-families
@@ -418,12 +432,12 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             if (fb && hL && hR && ry_f && rx_c && rz_w) err |= fb;
             const Flux Fyx = hllc(getF(ya.v, 0, tD), l, 1, gamma, igm1);
             putX(yb.v, 0, t, Fyx);
-            if (EX && hD && hL && hR && ry_f && rx_c && rz_w) mf_put(5, q, Fyx.m);
+            if (exb(5) && rz_w) mf_put(5, q, Fyx.m);
             l = corner_state(qy_lo, dF1z, fz3, gm1, igm1, fb);  // (y|z)
             if (fb && ry_f && rz_c && rx_w) err |= fb;
             const Flux Fyz = hllc(getF(ya.v, 5, tD), l, 1, gamma, igm1);
             putX(yb.v, 5, t, Fyz);
-            if (EX && hD && ry_f && rz_c && ex_x) mf_put(6, q, Fyz.m);
+            if (exb(6) && rz_c) mf_put(6, q, Fyz.m);
         }
         // z-families: the flux through the z-face between q-1 and q
         const bool rz_f = inr(q, 0, n2), rz_fh = inr(q + 1, 0, n2);
@@ -432,19 +446,17 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             Face l = corner_state(qz_lo, dF1x, fx3, gm1, igm1, fb);  // (z|x)
             if (fb && hL && hR && rz_f && rx_c && ry_w) err |= fb;
             Flux Fzx = hllc(c_zx_hi, l, 2, gamma, igm1);
+            if (exb(7) && q >= T.z0 && rz_f) mf_put(7, q, Fzx.m);
             Face h = corner_state(qz_hi, dF1x, fx3, gm1, igm1, fb);
             if (fb && hL && hR && rz_fh && rx_c && ry_w) err |= fb;
             c_zx_hi = h;
             l = corner_state(qz_lo, dF1y, fy3, gm1, igm1, fb);  // (z|y)
             if (fb && hD && hU && rz_f && ry_c && rx_w) err |= fb;
             Flux Fzy = hllc(c_zy_hi, l, 2, gamma, igm1);
+            if (exb(8) && q >= T.z0 && rz_f) mf_put(8, q, Fzy.m);
             h = corner_state(qz_hi, dF1y, fy3, gm1, igm1, fb);
             if (fb && hD && hU && rz_fh && ry_c && rx_w) err |= fb;
             c_zy_hi = h;
-            if (EX && q >= T.z0 && rz_f) {
-                if (hL && hR && rx_c && ex_y) mf_put(7, q, Fzx.m);
-                if (hD && hU && ry_c && ex_x) mf_put(8, q, Fzy.m);
-            }
             // z-differences of the (z|s) fluxes of plane q-1
             dzx = fdiff(Fzx, F2zx);
             dzy = fdiff(Fzy, F2zy);
@@ -461,7 +473,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, igm1, fb);
         if (fb && zin && rz_fh) err |= fb;
         const Flux F3zq = hllc(fz_hi, zl, 2, gamma, igm1);
-        if (EX && zin && q >= T.z0 && rz_f) mf_put(11, q, F3zq.m);
+        if (exb(11) && q >= T.z0 && rz_f) mf_put(11, q, F3zq.m);
         fz_hi = zh;
         // y-difference of the (y|z) fluxes of plane q (used next plane)
         const Flux dyz = fdiff(getX(yb.v, 5, tU), getX(yb.v, 5, t));
@@ -508,7 +520,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         Flux dux;
         {
             const Flux F3x = hllc(prevF(xh), xl, 0, gamma, igm1);
-            if (EX && pv && hL && hD && hU && rx_f && ry_c && rp_c) mf_put(9, p, F3x.m);
+            if (exb(9) && pv && rp_c) mf_put(9, p, F3x.m);
             const Flux d = next_minus(F3x);
             dux.m = ax * d.m;
             dux.mu = ax * d.mu;
@@ -522,7 +534,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             yd.ri = ya.v[5][tD];
             const Flux F3y = hllc(yd, yl, 1, gamma, igm1);
             putX(yb.v, 0, t, F3y);
-            if (EX && pv && hD && hL && hR && ry_f && rx_c && rp_c) mf_put(10, p, F3y.m);
+            if (exb(10) && pv && rp_c) mf_put(10, p, F3y.m);
         }
         __syncthreads();
         // ---------------------------------------------------- update plane p

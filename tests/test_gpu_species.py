@@ -68,6 +68,7 @@ CASES = {
     "smooth_ragged_4": (lambda: inputs.smooth((37, 29, 23), seed=6), 4),
     "sedov_flattened_2": (_flat(lambda: inputs.sedov(32)), 2),
     "one_cell_thin": (lambda: inputs.sod((1, 20, 5), axis=1), 1),
+    "kh_three_ghosts_8": (lambda: inputs.kh((20, 18, 22), seed=7, ng=3), 8),
 }
 
 
