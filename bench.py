@@ -140,7 +140,32 @@ def time_species(hydro, torch, inputs, steps, warmup, ns=2, n=256):
     sp_ms = st.get("species", 0.0)
     e = (n + 2) ** 3
     pass_bytes = 2 * (12 + 15 * ns) * 8 * e + 2 * 8 * ns * ncell
+    # the Sedov blast as a tiled level (256^3 in 64^3 boxes) with the same
+    # species count: both ghost exchanges and the batched species step
+    states, boxes, prm_s, lo, til = inputs.sedov_level(256, 64)
+    U0, box0, _ = inputs.sedov(256)
+    S0 = inputs.species(U0, box0, ns, seed=8)
+    sst, _, _, _ = inputs.tile(S0, box0, [inputs.even_cuts(256, 64)] * 3)
+    del U0, S0
+    tiling = hydro.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    lev = hydro.Level(states, boxes, prm_s, shared_dt=True, tiling=tiling, species=sst)
+    for _ in range(warmup):
+        lev.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        lev.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_lev = e0.elapsed_time(e1) / steps
+    err |= int(lev.err.item())
+    del lev
+    tiling.close()
+    torch.cuda.empty_cache()
     return {"species": ns, "cu_per_s": ncell * steps / (ms * 1e-3),
+            "sedov256_tiled_level_cu_per_s": 256 ** 3 / (ms_lev * 1e-3),
+            "sedov256_tiled_level_ms_per_step": ms_lev,
             "ms_per_step": ms / steps, "ms_per_step_without_species": ms0 / steps,
             "stage_ms": {k: round(v, 3) for k, v in st.items()},
             "species_pass_ms": sp_ms,

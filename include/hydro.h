@@ -172,6 +172,35 @@ hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const d
                                  double *dt_next_dev, void *ws_dev, size_t ws_bytes,
                                  void *sws_dev, size_t sws_bytes, int32_t *err_dev, void *stream);
 
+/* Species of a batch of boxes (the plan's boxes, in its order): the species
+ * workspace that advance_boxes_species needs for them (the sum of
+ * hydro_species_workspace_bytes over the boxes); 0 for invalid arguments. */
+size_t hydro_species_workspace_bytes_boxes(const hydro_box *boxes, int nb, int nspec);
+
+/* hydro_fill_ghosts_species for every box of a plan, each by its own
+ * boundary kinds, in one launch; S_ptrs_dev: device array of nb species
+ * pointers.  For boxes that tile one domain use
+ * hydro_fill_ghosts_level_species. */
+hydro_status hydro_fill_ghosts_boxes_species(int nb, double *const *S_ptrs_dev, int nspec,
+                                             const void *plan, void *stream);
+
+/* advance_boxes plus the species of every box (as advance_box_species does
+ * for one box): S_ptrs_dev / S_new_ptrs_dev are device arrays of nb species
+ * pointers (ghosts of the S arrays filled); the gas arguments and results
+ * are exactly those of advance_boxes.  sws_dev: at least
+ * hydro_species_workspace_bytes_boxes(boxes, nb, nspec) bytes (HYDRO_ENOWS
+ * otherwise), 256-byte aligned, not overlapping ws_dev (HYDRO_EINVAL); box
+ * b's part lies at the sum of the earlier boxes' sizes.  The S arrays of
+ * different boxes must not overlap, nor any S_new array any other array. */
+hydro_status advance_boxes_species(int nb, const double *const *U_ptrs_dev,
+                                   double *const *U_new_ptrs_dev,
+                                   const double *const *S_ptrs_dev,
+                                   double *const *S_new_ptrs_dev, int nspec, const void *plan,
+                                   const hydro_params *prm, const double *dt_dev, int dt_stride,
+                                   double *dt_next_dev, double *dt_next_min_dev, void *ws_dev,
+                                   size_t ws_bytes, void *sws_dev, size_t sws_bytes,
+                                   int32_t *err_dev, void *stream);
+
 /* Batched timestep over a list of boxes (a level of Sec. II's MultiFab):
  * fills the ghosts of every box, writes each box's dt to dt_dev[b] and, if
  * dt_min_dev is not NULL, the minimum over boxes to *dt_min_dev.
@@ -233,6 +262,12 @@ void hydro_level_destroy(void *level);
  * every box's new valid cells equal the whole domain's advanced as one box. */
 hydro_status hydro_fill_ghosts_level(int nb, double *const *U_ptrs_dev, const void *level,
                                      void *stream);
+
+/* The ghost exchange of hydro_fill_ghosts_level for the species arrays of
+ * the level's boxes (nspec components each, no sign flip at reflecting
+ * faces).  S_ptrs_dev: device array of nb species pointers. */
+hydro_status hydro_fill_ghosts_level_species(int nb, double *const *S_ptrs_dev, int nspec,
+                                             const void *level, void *stream);
 
 /* Plan for a fixed list of boxes: validates them, chooses the tile shapes
  * (autotune_json: NULL for the built-in choice, else a JSON object mapping

@@ -286,7 +286,7 @@ __device__ __forceinline__ Flux next_minus(const Flux &f)
 template <bool EX>
 __global__ void __launch_bounds__(kFT) __attribute__((amdgpu_waves_per_eu(HYDRO_FUSED_WAVES)))
 k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz, int *err_dev,
-             double *mflux)
+             double *mflux, const long long *mf_pre, int mf_mul)
 {
     // y-neighbour exchanges alternate between two buffers, so each needs one
     // barrier (its readers of two exchanges back are past the barrier of the
@@ -330,6 +330,8 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
     // mass-flux export: field f of face (x, y, z).  Bit f of exm: the lane
     // computes field f from valid data and its face lies in the field's
     // region (the plane's conditions are checked where the flux is formed).
+    // (a batch: box b's export starts mf_mul * mf_pre[b] doubles in)
+    if (EX && mf_pre) mflux += mf_mul * mf_pre[o.b];
     const long long mfE = EX ? mf_stride(n0, n1, n2) : 0;
     const long long mfP = (long long)(n0 + 2) * (n1 + 2);
     // (a uniform plane base plus the lane's 32-bit byte offset, as for the

@@ -541,10 +541,12 @@ hydro_status launch_status()
 }
 
 // the whole advance, given a launch template and per-stage grid sizes
-// (mflux: the mass-flux export of a single box for its species pass, or null)
+// (mflux: the mass-flux export for the species pass, or null; for a batch,
+// box b's part starts mf_mul * mf_pre[b] doubles in)
 hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *const *pre,
                              const int *const *order, const hydro_params *prm, int32_t *err32,
-                             hipStream_t st, double *mflux = nullptr)
+                             hipStream_t st, double *mflux = nullptr,
+                             const long long *mf_pre = nullptr, int mf_mul = 0)
 {
     int *err_dev = (int *)err32;
     const double gamma = prm->gamma;
@@ -568,11 +570,12 @@ hydro_status enqueue_advance(Launch L, const long long *grid, const unsigned *co
     prof(PG_FUSED, 0, st);
     if (mflux)
         hipLaunchKernelGGL(k_flux_fused<true>, set(ST_FLUX), dim3(kFT), 0, st, L, gamma,
-                           prm->cfl, prm->grav[0], prm->grav[1], prm->grav[2], err_dev, mflux);
+                           prm->cfl, prm->grav[0], prm->grav[1], prm->grav[2], err_dev, mflux,
+                           mf_pre, mf_mul);
     else
         hipLaunchKernelGGL(k_flux_fused<false>, set(ST_FLUX), dim3(kFT), 0, st, L, gamma,
                            prm->cfl, prm->grav[0], prm->grav[1], prm->grav[2], err_dev,
-                           (double *)nullptr);
+                           (double *)nullptr, (const long long *)nullptr, 0);
     prof(PG_FUSED, 1, st);
     return launch_status();
 }
@@ -657,20 +660,57 @@ bool parse_tiles(const char *js, std::vector<TileRule> &out)
 
 // ---------------------------------------------------------------- plans
 
+// species stages of a batch (blocks per box: ghost cells of the state
+// layout, cells / faces of the index box, valid cells)
+enum { SPS_FILL, SPS_TRACE, SPS_CORNER, SPS_FINAL, SPS_UPDATE, SPS_COUNT };
+
+__host__ inline long long species_stage_blocks(const Geo &g, int st)
+{
+    const long long nE = (long long)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
+    if (st == SPS_FILL) return (g.cs + kBlock - 1) / kBlock;
+    if (st == SPS_TRACE) return (nE + kBlock - 1) / kBlock;
+    if (st == SPS_CORNER) return sp_part_blocks(nE, 6);
+    if (st == SPS_FINAL) return sp_part_blocks(nE, 3);
+    return ((long long)g.n[0] * g.n[1] * g.n[2] + kBlock - 1) / kBlock;
+}
+
 struct Plan {
     int nb;
     std::vector<hydro_box> boxes;
     std::vector<Geo> geos;
     size_t ws_bytes;
     long long grid[ST_COUNT];  // total blocks per stage
+    long long sp_grid[SPS_COUNT];
+    long long etot;            // sum of the boxes' field strides (species arrays)
     // device buffer: [Geo nb][long long wsoff nb][int order ST_COUNT x nb]
-    // [unsigned pre ST_COUNT x (nb+1)]
+    // [unsigned pre ST_COUNT x (nb+1)][unsigned species pre SPS_COUNT x (nb+1)]
+    // [long long epre nb+1]
     void *dev;
     const Geo *geos_dev;
     const long long *wsoff_dev;
     const int *order_dev[ST_COUNT];
     const unsigned *pre_dev[ST_COUNT];
+    const unsigned *sp_pre_dev[SPS_COUNT];
+    const long long *epre_dev;
 };
+
+// the species pass (trace, corner, final, update) of one box (B.nb == 0)
+// or a batch (B with the plan's species prefixes)
+void enqueue_species(const SpArgs &A, SpBatch B, const long long *grid,
+                     const unsigned *const *pre, int32_t *err_dev, hipStream_t st)
+{
+    auto set = [&](int s) {
+        if (B.nb) B.pre = pre[s];
+        return dim3((unsigned)grid[s]);
+    };
+    prof(PG_SPECIES, 0, st);
+    hipLaunchKernelGGL(k_sp_trace, set(SPS_TRACE), dim3(kBlock), 0, st, A, B);
+    hipLaunchKernelGGL(k_sp_corner, set(SPS_CORNER), dim3(kBlock), 0, st, A, B);
+    hipLaunchKernelGGL(k_sp_final, set(SPS_FINAL), dim3(kBlock), 0, st, A, B);
+    hipLaunchKernelGGL(k_sp_update, set(SPS_UPDATE), dim3(kBlock), 0, st, A, B,
+                       (int *)err_dev);
+    prof(PG_SPECIES, 1, st);
+}
 
 }  // namespace
 
@@ -767,9 +807,15 @@ hydro_status hydro_fill_ghosts_species(double *S_dev, int nspec, const hydro_box
                                        void *stream)
 {
     if (!S_dev || nspec < 1 || nspec > kMaxSpecies || !box_valid(box)) return HYDRO_EINVAL;
-    const Geo g = make_geo(box);
-    hipLaunchKernelGGL(k_sp_fill, dim3((unsigned)((g.cs + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       (hipStream_t)stream, g, S_dev, nspec);
+    SpArgs A;
+    memset(&A, 0, sizeof A);
+    A.g = make_geo(box);
+    A.S = S_dev;
+    A.ns = nspec;
+    SpBatch B;
+    memset(&B, 0, sizeof B);
+    hipLaunchKernelGGL(k_sp_fill, dim3((unsigned)species_stage_blocks(A.g, SPS_FILL)),
+                       dim3(kBlock), 0, (hipStream_t)stream, A, B);
     return launch_status();
 }
 
@@ -813,6 +859,7 @@ hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const d
     if (rc != HYDRO_OK) return rc;
     // the species pass
     SpArgs A;
+    memset(&A, 0, sizeof A);
     A.g = g;
     A.U = U_dev;
     A.S = S_dev;
@@ -827,15 +874,11 @@ hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const d
     A.ns = nspec;
     A.flat = prm->flatten;
     A.gamma = prm->gamma;
-    const long long nE = (long long)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
-    const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
-    const dim3 gE((unsigned)((nE + kBlock - 1) / kBlock)), gV((unsigned)((nv + kBlock - 1) / kBlock));
-    prof(PG_SPECIES, 0, st);
-    hipLaunchKernelGGL(k_sp_trace, gE, dim3(kBlock), 0, st, A);
-    hipLaunchKernelGGL(k_sp_corner, dim3(sp_part_blocks(nE, 6)), dim3(kBlock), 0, st, A);
-    hipLaunchKernelGGL(k_sp_final, dim3(sp_part_blocks(nE, 3)), dim3(kBlock), 0, st, A);
-    hipLaunchKernelGGL(k_sp_update, gV, dim3(kBlock), 0, st, A, (int *)err_dev);
-    prof(PG_SPECIES, 1, st);
+    long long grid_sp[SPS_COUNT];
+    for (int s = 0; s < SPS_COUNT; ++s) grid_sp[s] = species_stage_blocks(g, s);
+    SpBatch B;
+    memset(&B, 0, sizeof B);
+    enqueue_species(A, B, grid_sp, nullptr, err_dev, st);
     return launch_status();
 }
 
@@ -903,11 +946,33 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
         pre[(size_t)s * (nb + 1) + nb] = (unsigned)acc;
         P->grid[s] = (long long)acc;
     }
+    // the species stages take the boxes in the given order
+    std::vector<unsigned> spre((size_t)SPS_COUNT * (nb + 1));
+    std::vector<long long> epre(nb + 1);
+    for (int s = 0; s < SPS_COUNT; ++s) {
+        unsigned long long acc = 0;
+        for (int b = 0; b < nb; ++b) {
+            spre[(size_t)s * (nb + 1) + b] = (unsigned)acc;
+            acc += (unsigned long long)species_stage_blocks(P->geos[b], s);
+        }
+        if (acc >= (1ULL << 31)) {
+            delete P;
+            return HYDRO_EINVAL;
+        }
+        spre[(size_t)s * (nb + 1) + nb] = (unsigned)acc;
+        P->sp_grid[s] = (long long)acc;
+    }
+    epre[0] = 0;
+    for (int b = 0; b < nb; ++b)
+        epre[b + 1] = epre[b] + mf_stride(P->geos[b].n[0], P->geos[b].n[1], P->geos[b].n[2]);
+    P->etot = epre[nb];
     size_t szg = sizeof(Geo) * nb, szw = sizeof(long long) * nb,
-           szo = sizeof(int) * order.size(), szp = sizeof(unsigned) * pre.size();
+           szo = sizeof(int) * order.size(), szp = sizeof(unsigned) * pre.size(),
+           szs = sizeof(unsigned) * spre.size(), sze = sizeof(long long) * epre.size();
     size_t offw = (szg + 255) / 256 * 256, offo = offw + (szw + 255) / 256 * 256,
-           offp = offo + (szo + 255) / 256 * 256;
-    if (hipMalloc(&P->dev, offp + szp) != hipSuccess) {
+           offp = offo + (szo + 255) / 256 * 256, offs = offp + (szp + 255) / 256 * 256,
+           offe = offs + (szs + 255) / 256 * 256;
+    if (hipMalloc(&P->dev, offe + sze) != hipSuccess) {
         delete P;
         return HYDRO_EHIP;
     }
@@ -915,7 +980,9 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
     if (hipMemcpy(base, P->geos.data(), szg, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + offw, wsoff.data(), szw, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(base + offo, order.data(), szo, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(base + offp, pre.data(), szp, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(base + offp, pre.data(), szp, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + offs, spre.data(), szs, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + offe, epre.data(), sze, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(P->dev);
         delete P;
         return HYDRO_EHIP;
@@ -926,6 +993,9 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
         P->order_dev[s] = (const int *)(base + offo) + (size_t)s * nb;
     for (int s = 0; s < ST_COUNT; ++s)
         P->pre_dev[s] = (const unsigned *)(base + offp) + (size_t)s * (nb + 1);
+    for (int s = 0; s < SPS_COUNT; ++s)
+        P->sp_pre_dev[s] = (const unsigned *)(base + offs) + (size_t)s * (nb + 1);
+    P->epre_dev = (const long long *)(base + offe);
     *plan_out = P;
     return HYDRO_OK;
 }
@@ -1006,6 +1076,98 @@ hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
     L.dtn_min = (unsigned long long *)dt_next_min_dev;
     return enqueue_advance(L, P->grid, P->pre_dev, P->order_dev, prm, err_dev,
                            (hipStream_t)stream);
+}
+
+size_t hydro_species_workspace_bytes_boxes(const hydro_box *boxes, int nb, int nspec)
+{
+    if (!boxes || nb < 1) return 0;
+    size_t tot = 0;
+    for (int b = 0; b < nb; ++b) {
+        const size_t n = hydro_species_workspace_bytes(&boxes[b], nspec);
+        if (!n) return 0;
+        tot += n;
+    }
+    return tot;
+}
+
+hydro_status hydro_fill_ghosts_boxes_species(int nb, double *const *S_ptrs_dev, int nspec,
+                                             const void *plan, void *stream)
+{
+    const Plan *P = (const Plan *)plan;
+    if (!P || nb != P->nb || !S_ptrs_dev || nspec < 1 || nspec > kMaxSpecies)
+        return HYDRO_EINVAL;
+    SpArgs A;
+    memset(&A, 0, sizeof A);
+    A.ns = nspec;
+    SpBatch B;
+    memset(&B, 0, sizeof B);
+    B.nb = nb;
+    B.pre = P->sp_pre_dev[SPS_FILL];
+    B.geos = P->geos_dev;
+    B.Ss = (const double *const *)S_ptrs_dev;
+    hipLaunchKernelGGL(k_sp_fill, dim3((unsigned)P->sp_grid[SPS_FILL]), dim3(kBlock), 0,
+                       (hipStream_t)stream, A, B);
+    return launch_status();
+}
+
+hydro_status advance_boxes_species(int nb, const double *const *U_ptrs_dev,
+                                   double *const *U_new_ptrs_dev,
+                                   const double *const *S_ptrs_dev,
+                                   double *const *S_new_ptrs_dev, int nspec, const void *plan,
+                                   const hydro_params *prm, const double *dt_dev, int dt_stride,
+                                   double *dt_next_dev, double *dt_next_min_dev, void *ws_dev,
+                                   size_t ws_bytes, void *sws_dev, size_t sws_bytes,
+                                   int32_t *err_dev, void *stream)
+{
+    const Plan *P = (const Plan *)plan;
+    if (!P || nb != P->nb || !S_ptrs_dev || !S_new_ptrs_dev || !sws_dev || nspec < 1 ||
+        nspec > kMaxSpecies || ((uintptr_t)sws_dev & 255) ||
+        (ws_dev && overlaps(sws_dev, sws_bytes, ws_dev, ws_bytes)))
+        return HYDRO_EINVAL;
+    if (sws_bytes < (size_t)(12 + 15 * nspec) * (size_t)P->etot * sizeof(double))
+        return HYDRO_ENOWS;
+    if (!U_ptrs_dev || !U_new_ptrs_dev || !dt_dev || !ws_dev || !err_dev ||
+        !params_valid(prm) || (dt_stride != 0 && dt_stride != 1) ||
+        (dt_next_min_dev && !dt_next_dev) || !flatten_ok(prm, P->boxes.data(), P->nb))
+        return HYDRO_EINVAL;
+    {
+        const size_t ndt = (dt_stride ? (size_t)nb : 1) * sizeof(double);
+        const size_t nn = (size_t)nb * sizeof(double);
+        if (dt_next_dev && overlaps(dt_next_dev, nn, dt_dev, ndt)) return HYDRO_EINVAL;
+        if (dt_next_min_dev && (overlaps(dt_next_min_dev, sizeof(double), dt_dev, ndt) ||
+                                overlaps(dt_next_min_dev, sizeof(double), dt_next_dev, nn)))
+            return HYDRO_EINVAL;
+    }
+    if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
+    if (ws_bytes < P->ws_bytes) return HYDRO_ENOWS;
+    const hipStream_t st = (hipStream_t)stream;
+    Launch L = batch_launch(P, (double *const *)U_ptrs_dev, U_new_ptrs_dev, ws_dev, dt_dev,
+                            dt_stride);
+    L.dtn = (unsigned long long *)dt_next_dev;
+    L.dtn_min = (unsigned long long *)dt_next_min_dev;
+    hydro_status rc = enqueue_advance(L, P->grid, P->pre_dev, P->order_dev, prm, err_dev, st,
+                                      (double *)sws_dev, P->epre_dev, 12 + 15 * nspec);
+    if (rc != HYDRO_OK) return rc;
+    SpArgs A;
+    memset(&A, 0, sizeof A);
+    A.ns = nspec;
+    A.flat = prm->flatten;
+    A.gamma = prm->gamma;
+    SpBatch B;
+    memset(&B, 0, sizeof B);
+    B.nb = nb;
+    B.geos = P->geos_dev;
+    B.Us = U_ptrs_dev;
+    B.Ss = S_ptrs_dev;
+    B.Sns = S_new_ptrs_dev;
+    B.ws = (const char *)ws_dev;
+    B.wsoff = P->wsoff_dev;
+    B.sws = (double *)sws_dev;
+    B.epre = P->epre_dev;
+    B.dts = dt_dev;
+    B.dt_stride = dt_stride;
+    enqueue_species(A, B, P->sp_grid, P->sp_pre_dev, err_dev, st);
+    return launch_status();
 }
 
 hydro_status hydro_fill_ghosts_boxes(int nb, double *const *U_ptrs_dev, const void *plan,

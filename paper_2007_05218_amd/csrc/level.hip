@@ -71,7 +71,17 @@ __device__ __forceinline__ long long lcell(const LBox &B, int i, int j, int k)
     return ((long long)(k + B.ng) * B.s1 + (j + B.ng)) * B.s0 + (i + B.ng);
 }
 
-__global__ void __launch_bounds__(kLBlock) k_fill_level(LevelArgs L, double *const *Us)
+// The ghost cell this thread fills: box b (block prefix search), the cell
+// (i, j, k) in box coordinates, its source box o and source cell, and the
+// reflections (fx, fy, fz) on the way.  False for threads past the box's
+// ghost cells.
+struct LGhost {
+    int b, o;
+    long long dst, src;
+    int fx, fy, fz;
+};
+
+__device__ __forceinline__ bool level_ghost(const LevelArgs &L, LGhost &G)
 {
     int b = 0, hi = L.nb;
     const unsigned x = blockIdx.x;
@@ -86,7 +96,7 @@ __global__ void __launch_bounds__(kLBlock) k_fill_level(LevelArgs L, double *con
     const long long cz = ng2 * s1 * s0;
     const long long cy = (long long)B.n[2] * ng2 * s0;
     const long long cx = (long long)B.n[2] * B.n[1] * ng2;
-    if (t >= cz + cy + cx) return;
+    if (t >= cz + cy + cx) return false;
     int i, j, k;
     if (t < cz) {
         i = (int)(t % s0) - B.ng;
@@ -109,23 +119,46 @@ __global__ void __launch_bounds__(kLBlock) k_fill_level(LevelArgs L, double *con
         j = (int)(t % B.n[1]);
         k = (int)(t / B.n[1]);
     }
-    int fx = 0, fy = 0, fz = 0;
-    const int sx = dom_src(B.lo[0] + i, L.dom[0], L.bc_lo[0], L.bc_hi[0], fx);
-    const int sy = dom_src(B.lo[1] + j, L.dom[1], L.bc_lo[1], L.bc_hi[1], fy);
-    const int sz = dom_src(B.lo[2] + k, L.dom[2], L.bc_lo[2], L.bc_hi[2], fz);
+    G.fx = G.fy = G.fz = 0;
+    const int sx = dom_src(B.lo[0] + i, L.dom[0], L.bc_lo[0], L.bc_hi[0], G.fx);
+    const int sy = dom_src(B.lo[1] + j, L.dom[1], L.bc_lo[1], L.bc_hi[1], G.fy);
+    const int sz = dom_src(B.lo[2] + k, L.dom[2], L.bc_lo[2], L.bc_hi[2], G.fz);
     const int o = L.owner[((long long)(sz / L.G) * L.om1 + sy / L.G) * L.om0 + sx / L.G];
     const LBox S = L.bx[o];
-    const double *U = Us[o];
-    double *V = Us[b];
-    const long long src = lcell(S, sx - S.lo[0], sy - S.lo[1], sz - S.lo[2]);
-    const long long dst = lcell(B, i, j, k);
-    const double r = U[src], mu = U[S.cs + src], mv = U[2 * S.cs + src],
-                 mw = U[3 * S.cs + src], e = U[4 * S.cs + src];
+    G.b = b;
+    G.o = o;
+    G.src = lcell(S, sx - S.lo[0], sy - S.lo[1], sz - S.lo[2]);
+    G.dst = lcell(B, i, j, k);
+    return true;
+}
+
+__global__ void __launch_bounds__(kLBlock) k_fill_level(LevelArgs L, double *const *Us)
+{
+    LGhost G;
+    if (!level_ghost(L, G)) return;
+    const long long scs = L.bx[G.o].cs, dcs = L.bx[G.b].cs;
+    const double *U = Us[G.o];
+    double *V = Us[G.b];
+    const long long src = G.src, dst = G.dst;
+    const double r = U[src], mu = U[scs + src], mv = U[2 * scs + src],
+                 mw = U[3 * scs + src], e = U[4 * scs + src];
     V[dst] = r;
-    V[B.cs + dst] = fx ? -mu : mu;
-    V[2 * B.cs + dst] = fy ? -mv : mv;
-    V[3 * B.cs + dst] = fz ? -mw : mw;
-    V[4 * B.cs + dst] = e;
+    V[dcs + dst] = G.fx ? -mu : mu;
+    V[2 * dcs + dst] = G.fy ? -mv : mv;
+    V[3 * dcs + dst] = G.fz ? -mw : mw;
+    V[4 * dcs + dst] = e;
+}
+
+// the same for ns species components (no sign flip)
+__global__ void __launch_bounds__(kLBlock) k_fill_level_species(LevelArgs L, double *const *Ss,
+                                                                  int ns)
+{
+    LGhost G;
+    if (!level_ghost(L, G)) return;
+    const long long scs = L.bx[G.o].cs, dcs = L.bx[G.b].cs;
+    const double *S = Ss[G.o];
+    double *V = Ss[G.b];
+    for (int c = 0; c < ns; ++c) V[c * dcs + G.dst] = S[c * scs + G.src];
 }
 
 struct LevelPlan {
@@ -253,6 +286,17 @@ hydro_status hydro_fill_ghosts_level(int nb, double *const *U_ptrs_dev, const vo
     if (P->blocks == 0) return HYDRO_OK;
     hipLaunchKernelGGL(k_fill_level, dim3((unsigned)P->blocks), dim3(kLBlock), 0,
                        (hipStream_t)stream, P->args, U_ptrs_dev);
+    return hipGetLastError() == hipSuccess ? HYDRO_OK : HYDRO_EHIP;
+}
+
+hydro_status hydro_fill_ghosts_level_species(int nb, double *const *S_ptrs_dev, int nspec,
+                                             const void *level, void *stream)
+{
+    const LevelPlan *P = (const LevelPlan *)level;
+    if (!P || nb != P->nb || !S_ptrs_dev || nspec < 1 || nspec > 8) return HYDRO_EINVAL;
+    if (P->blocks == 0) return HYDRO_OK;
+    hipLaunchKernelGGL(k_fill_level_species, dim3((unsigned)P->blocks), dim3(kLBlock), 0,
+                       (hipStream_t)stream, P->args, S_ptrs_dev, nspec);
     return hipGetLastError() == hipSuccess ? HYDRO_OK : HYDRO_EHIP;
 }
 

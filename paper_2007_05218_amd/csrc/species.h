@@ -47,6 +47,61 @@ struct SpArgs {
     double gamma;
 };
 
+// A batch of boxes (nb >= 1; nb == 0: the single box of SpArgs).  Each
+// species stage's blocks are dealt to the boxes by the plan's prefix sums;
+// box b's species arrays start (12 + 15 ns) * epre[b] doubles into the
+// species workspace (epre: the prefix of the boxes' field strides).
+struct SpBatch {
+    int nb;
+    const unsigned *pre;  // this stage's block prefix, nb+1 entries
+    const Geo *geos;
+    const double *const *Us;
+    const double *const *Ss;
+    double *const *Sns;
+    const char *ws;
+    const long long *wsoff;  // doubles from the workspace base
+    double *sws;
+    const long long *epre;
+    const double *dts;
+    int dt_stride;
+};
+
+// this block's box (A rewritten for it) and block index within the box
+__device__ __forceinline__ long long sp_box(SpArgs &A, const SpBatch &B)
+{
+    if (B.nb == 0) return blockIdx.x;
+    int lo = 0, hi = B.nb;
+    const unsigned x = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (B.pre[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    const int b = lo;
+    A.g = B.geos[b];
+    A.U = B.Us ? B.Us[b] : nullptr;
+    A.S = B.Ss ? B.Ss[b] : nullptr;
+    A.Sn = B.Sns ? B.Sns[b] : nullptr;
+    A.ws = B.ws ? B.ws + B.wsoff[b] * (long long)sizeof(double) : nullptr;
+    A.E = mf_stride(A.g.n[0], A.g.n[1], A.g.n[2]);
+    if (B.sws) {
+        A.mf = B.sws + (12 + 15 * (long long)A.ns) * B.epre[b];
+        A.Xt = const_cast<double *>(A.mf) + 12 * A.E;
+        A.G2 = A.Xt + 6 * A.ns * A.E;
+        A.G3 = A.G2 + 6 * A.ns * A.E;
+    }
+    A.dt = B.dts ? B.dts + (long long)b * B.dt_stride : nullptr;
+    return (long long)(x - B.pre[b]);
+}
+
+// component a (0, 1, 2) of a 3-vector by selects, not by indexing (a
+// runtime index into the box's geometry would put it in scratch memory)
+template <typename T>
+__device__ __forceinline__ T sel3(const T (&v)[3], int a)
+{
+    return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
+}
+
 __device__ __forceinline__ bool sp_decode(const SpArgs &A, long long t, int &x, int &y, int &z)
 {
     const int e0 = A.g.n[0] + 2, e1 = A.g.n[1] + 2, e2 = A.g.n[2] + 2;
@@ -75,13 +130,12 @@ __device__ __forceinline__ double sp_rho_traced(const SpArgs &A, int d, int side
     return ws_ld(w.plane(z), w.off(x, y), side ? QLO(d, 0) : QHI(d, 0));
 }
 
-// Block b of a stage with nf parts per face (flux families or axes): part
-// (b / 8) % nf of cell block ((b / 8) / nf) * 8 + b % 8.  Blocks are dealt to
+// Block b (within its box) of a stage with nf parts per face (flux families
+// or axes): part (b / 8) % nf of cell block ((b / 8) / nf) * 8 + b % 8.  Blocks are dealt to
 // the 8 XCDs round-robin (b % 8), so the nf parts of one cell block run on
 // one XCD, close in time, and share what they read in its L2.
-__device__ __forceinline__ long long sp_part(int nf, int &part)
+__device__ __forceinline__ long long sp_part(long long b, int nf, int &part)
 {
-    const long long b = blockIdx.x;
     const long long r = b / 8;
     part = (int)(r % nf);
     return ((r / nf) * 8 + b % 8) * kBlock + threadIdx.x;
@@ -96,10 +150,10 @@ __host__ inline unsigned sp_part_blocks(long long items, int nf)
 // stage inverts it as t = fam / 2, s = fam % 2 (+1 when >= t)
 __host__ __device__ constexpr int sp_fam(int t, int s) { return 2 * t + (s > t ? s - 1 : s); }
 
-__global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A)
+__global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A, SpBatch B)
 {
     int x, y, z;
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long t = sp_box(A, B) * kBlock + threadIdx.x;
     if (!sp_decode(A, t, x, y, z)) return;
     const Geo &g = A.g;
     const double gm1 = A.gamma - 1.0;
@@ -134,16 +188,16 @@ __global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A)
 // flux difference across their cell along sd (the round-1 species flux
 // through an sd-face is its mass flux times the traced X of the side the
 // mass leaves), then the round-2 species flux through the face.
-__global__ void __launch_bounds__(kBlock) k_sp_corner(SpArgs A)
+__global__ void __launch_bounds__(kBlock) k_sp_corner(SpArgs A, SpBatch B)
 {
     int p[3], fam;
-    const long long t = sp_part(6, fam);
+    const long long t = sp_part(sp_box(A, B), 6, fam);
     if (!sp_decode(A, t, p[0], p[1], p[2])) return;
     const int td = fam / 2, sd = (fam % 2) < td ? (fam % 2) : (fam % 2) + 1;
-    const int *n = A.g.n;
     // faces of the family: td in [0, n], sd in [0, n), the third axis in [-1, n]
-    if (p[td] < 0 || p[sd] < 0 || p[sd] >= n[sd]) return;
-    const double fac = *A.dt / (3.0 * A.g.dx[sd]);
+    const int ptd = sel3(p, td), psd = sel3(p, sd);
+    if (ptd < 0 || psd < 0 || psd >= sel3(A.g.n, sd)) return;
+    const double fac = *A.dt / (3.0 * sel3(A.g.dx, sd));
     const double *F1 = A.mf + sd * A.E;
     long long ic[2], iu[2], il[2];  // the side's cell, its sd-neighbours above and below
     double Fl[2], Fh[2], rq[2], den[2];
@@ -184,18 +238,18 @@ __global__ void __launch_bounds__(kBlock) k_sp_corner(SpArgs A)
 // Final stage: one part per axis d.  Each thread takes one d-face: both
 // sides' traced X corrected by dt/2 of the two round-2 transverse species
 // flux differences, then the round-3 species flux through the face.
-__global__ void __launch_bounds__(kBlock) k_sp_final(SpArgs A)
+__global__ void __launch_bounds__(kBlock) k_sp_final(SpArgs A, SpBatch B)
 {
     int p[3], d;
-    const long long t = sp_part(3, d);
+    const long long t = sp_part(sp_box(A, B), 3, d);
     if (!sp_decode(A, t, p[0], p[1], p[2])) return;
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    const int *n = A.g.n;
     // faces: d in [0, n], the transverse axes in [0, n)
-    if (p[d] < 0 || p[t1] < 0 || p[t1] >= n[t1] || p[t2] < 0 || p[t2] >= n[t2]) return;
+    const int pd = sel3(p, d), p1 = sel3(p, t1), p2 = sel3(p, t2);
+    if (pd < 0 || p1 < 0 || p1 >= sel3(A.g.n, t1) || p2 < 0 || p2 >= sel3(A.g.n, t2)) return;
     const double dt = *A.dt;
-    const double f1 = dt / (2.0 * A.g.dx[t1]);
-    const double f2 = dt / (2.0 * A.g.dx[t2]);
+    const double f1 = dt / (2.0 * sel3(A.g.dx, t1));
+    const double f2 = dt / (2.0 * sel3(A.g.dx, t2));
     const int fa = sp_fam(t1, t2), fb = sp_fam(t2, t1);
     long long ic[2], i1[2], i2[2];
     double rq[2], den[2];
@@ -230,10 +284,10 @@ __global__ void __launch_bounds__(kBlock) k_sp_final(SpArgs A)
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_sp_update(SpArgs A, int *err_dev)
+__global__ void __launch_bounds__(kBlock) k_sp_update(SpArgs A, SpBatch B, int *err_dev)
 {
+    long long t = sp_box(A, B) * kBlock + threadIdx.x;
     const Geo &g = A.g;
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long nv = (long long)g.n[0] * g.n[1] * g.n[2];
     if (t >= nv) return;
     const int x = (int)(t % g.n[0]);
@@ -263,9 +317,12 @@ __global__ void __launch_bounds__(kBlock) k_sp_update(SpArgs A, int *err_dev)
 
 // ghost cells of the species array: the gas's boundary rules without any
 // sign flip (each ghost cell copies the cell its per-axis mapping names)
-__global__ void __launch_bounds__(kBlock) k_sp_fill(Geo g, double *S, int ns)
+__global__ void __launch_bounds__(kBlock) k_sp_fill(SpArgs A, SpBatch B)
 {
-    long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long t = sp_box(A, B) * kBlock + threadIdx.x;
+    const Geo &g = A.g;
+    double *S = const_cast<double *>(A.S);
+    const int ns = A.ns;
     if (t >= g.cs) return;
     const int i = (int)(t % g.s[0]) - g.ng;
     const long long r = t / g.s[0];

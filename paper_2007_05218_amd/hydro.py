@@ -26,7 +26,9 @@ EXPORTS = ("hydro_state_elems", "hydro_workspace_bytes", "hydro_fill_ghosts", "e
            "hydro_plan_destroy", "hydro_status_string", "hydro_stage_count",
            "hydro_stage_name", "hydro_set_stage_events", "hydro_fill_ghosts_boxes",
            "hydro_level_create", "hydro_level_destroy", "hydro_fill_ghosts_level",
-           "hydro_species_workspace_bytes", "hydro_fill_ghosts_species", "advance_box_species")
+           "hydro_species_workspace_bytes", "hydro_fill_ghosts_species", "advance_box_species",
+           "hydro_species_workspace_bytes_boxes", "hydro_fill_ghosts_boxes_species",
+           "advance_boxes_species", "hydro_fill_ghosts_level_species")
 
 
 class HydroBox(C.Structure):
@@ -92,10 +94,18 @@ def lib():
         L.hydro_fill_ghosts_species.argtypes = [vp, C.c_int, bp, vp]
         L.advance_box_species.argtypes = [vp, vp, vp, vp, C.c_int, bp, pp, vp, vp, vp,
                                           C.c_size_t, vp, C.c_size_t, vp, vp]
+        L.hydro_species_workspace_bytes_boxes.argtypes = [bp, C.c_int, C.c_int]
+        L.hydro_species_workspace_bytes_boxes.restype = C.c_size_t
+        L.hydro_fill_ghosts_boxes_species.argtypes = [C.c_int, vp, C.c_int, vp, vp]
+        L.advance_boxes_species.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, vp, pp, vp,
+                                            C.c_int, vp, vp, vp, C.c_size_t, vp, C.c_size_t,
+                                            vp, vp]
+        L.hydro_fill_ghosts_level_species.argtypes = [C.c_int, vp, C.c_int, vp, vp]
         for f in ("hydro_fill_ghosts", "estimate_dt", "advance_box", "estimate_dt_boxes",
                   "advance_boxes", "hydro_plan_create", "hydro_fill_ghosts_boxes",
                   "hydro_level_create", "hydro_fill_ghosts_level", "hydro_fill_ghosts_species",
-                  "advance_box_species"):
+                  "advance_box_species", "hydro_fill_ghosts_boxes_species",
+                  "advance_boxes_species", "hydro_fill_ghosts_level_species"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -336,6 +346,30 @@ def advance_boxes(plan, U_ptrs, Unew_ptrs, prm, dt, ws, err, dt_stride=1, stream
         _ptr(ws, torch.uint8), ws.numel(), _ptr(err, torch.int32), _stream(stream)))
 
 
+def species_workspace_bytes_boxes(boxes, nspec):
+    arr = (HydroBox * len(boxes))(*[make_box(b) for b in boxes])
+    return int(lib().hydro_species_workspace_bytes_boxes(arr, len(boxes), int(nspec)))
+
+
+def fill_ghosts_boxes_species(plan, S_ptrs, nspec, stream=None):
+    """Species ghost fill of every box of the plan (one launch)."""
+    _check("hydro_fill_ghosts_boxes_species", lib().hydro_fill_ghosts_boxes_species(
+        plan.nb, _ptr(S_ptrs, torch.int64), int(nspec), plan.handle, _stream(stream)))
+
+
+def advance_boxes_species(plan, U_ptrs, Unew_ptrs, S_ptrs, Snew_ptrs, nspec, prm, dt, ws, sws,
+                          err, dt_stride=1, stream=None, dt_next=None, dt_next_min=None):
+    """advance_boxes plus the species of every box."""
+    _check("advance_boxes_species", lib().advance_boxes_species(
+        plan.nb, _ptr(U_ptrs, torch.int64), _ptr(Unew_ptrs, torch.int64),
+        _ptr(S_ptrs, torch.int64), _ptr(Snew_ptrs, torch.int64), int(nspec), plan.handle,
+        C.byref(make_params(prm)), _ptr(dt), dt_stride,
+        _ptr(dt_next) if dt_next is not None else None,
+        _ptr(dt_next_min) if dt_next_min is not None else None,
+        _ptr(ws, torch.uint8), ws.numel(), _ptr(sws, torch.uint8), sws.numel(),
+        _ptr(err, torch.int32), _stream(stream)))
+
+
 def fill_ghosts_boxes(plan, U_ptrs, stream=None):
     """Ghost fill of every box of the plan (one launch)."""
     _check("hydro_fill_ghosts_boxes", lib().hydro_fill_ghosts_boxes(
@@ -381,6 +415,12 @@ def fill_ghosts_level(tiling, U_ptrs, stream=None):
         tiling.nb, _ptr(U_ptrs, torch.int64), tiling.handle, _stream(stream)))
 
 
+def fill_ghosts_level_species(tiling, S_ptrs, nspec, stream=None):
+    """Species ghost exchange between the boxes of a tiled level (one launch)."""
+    _check("hydro_fill_ghosts_level_species", lib().hydro_fill_ghosts_level_species(
+        tiling.nb, _ptr(S_ptrs, torch.int64), int(nspec), tiling.handle, _stream(stream)))
+
+
 class Level:
     """A list of boxes advanced together (a level of boxes): states and
     workspace on the device, one launch per stage for all boxes.
@@ -388,10 +428,12 @@ class Level:
     Without ``tiling`` the boxes are independent (each fills its own ghosts
     from its boundary kinds); with a ``Tiling`` of the same boxes they tile one
     domain, the ghosts come from the neighbouring boxes (hydro_fill_ghosts_level)
-    and the timestep is shared."""
+    and the timestep is shared.  ``species`` (optional): one host array of
+    partial densities per box (shape (nspec,) + the box's spatial shape),
+    advanced with the gas (advance_boxes_species)."""
 
     def __init__(self, states, boxes, prm, shared_dt=True, device="cuda", autotune_json=None,
-                 tiling=None):
+                 tiling=None, species=None):
         if tiling is not None and (not shared_dt or tiling.nb != len(boxes)):
             raise ValueError("a tiled level needs a tiling of its boxes and a shared timestep")
         self.tiling = tiling
@@ -409,6 +451,19 @@ class Level:
         self.err = torch.zeros(1, dtype=torch.int32, device=device)
         self.shared_dt = shared_dt
         self.have_dt = False  # dt_next / dt_next_min hold the current states' timesteps
+        self.S = None
+        if species is not None:
+            self.S = [torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
+                      for x in species]
+            self.nspec = self.S[0].shape[0]
+            if len(self.S) != len(self.U) or any(x.shape[0] != self.nspec for x in self.S):
+                raise ValueError("one species array per box, all with the same count")
+            self.Snew = [torch.empty_like(x) for x in self.S]
+            self.sa = pointer_array(self.S, device)
+            self.sb = pointer_array(self.Snew, device)
+            self.sws = torch.empty(max(species_workspace_bytes_boxes(self.plan.boxes,
+                                                                     self.nspec), 256),
+                                   dtype=torch.uint8, device=device)
 
     def step(self, stream=None):
         """Ghost fill + timesteps + advance of every box (the timesteps of
@@ -424,13 +479,22 @@ class Level:
             estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, self.dt_min, stream)
         if self.tiling is not None:
             fill_ghosts_level(self.tiling, self.pa, stream)
-        if self.shared_dt:
-            advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt_min, self.ws, self.err,
-                          dt_stride=0, stream=stream, dt_next=self.dt_next,
-                          dt_next_min=self.dt_next_min)
+        dt, stride = (self.dt_min, 0) if self.shared_dt else (self.dt, 1)
+        dtnm = self.dt_next_min if self.shared_dt else None
+        if self.S is None:
+            advance_boxes(self.plan, self.pa, self.pb, self.prm, dt, self.ws, self.err,
+                          dt_stride=stride, stream=stream, dt_next=self.dt_next,
+                          dt_next_min=dtnm)
         else:
-            advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt, self.ws, self.err,
-                          dt_stride=1, stream=stream, dt_next=self.dt_next)
+            if self.tiling is not None:
+                fill_ghosts_level_species(self.tiling, self.sa, self.nspec, stream)
+            else:
+                fill_ghosts_boxes_species(self.plan, self.sa, self.nspec, stream)
+            advance_boxes_species(self.plan, self.pa, self.pb, self.sa, self.sb, self.nspec,
+                                  self.prm, dt, self.ws, self.sws, self.err, dt_stride=stride,
+                                  stream=stream, dt_next=self.dt_next, dt_next_min=dtnm)
+            self.S, self.Snew = self.Snew, self.S
+            self.sa, self.sb = self.sb, self.sa
         self.U, self.Unew = self.Unew, self.U
         self.pa, self.pb = self.pb, self.pa
         self.have_dt = True
@@ -446,6 +510,9 @@ class Level:
 
     def states(self):
         return [u.cpu().numpy() for u in self.U]
+
+    def species(self):
+        return [x.cpu().numpy() for x in self.S]
 
 
 class StageTimer:

@@ -234,7 +234,8 @@ def sedov(n=64, r0_cells=2.0, p_amb=1e-5, e_blast=1.0, ng=NG):
 # ---------------------------------------------------------------------------
 
 def tile(U, box, cuts):
-    """Split the state U of a domain box into boxes that tile it: ``cuts[d]``
+    """Split the state U of a domain box (or its species array) into boxes
+    that tile it: ``cuts[d]``
     lists the cut positions along axis d (first 0, last n_d).  Returns
     (states, boxes, lo, tiling): box states with zero ghost cells, box
     descriptions (the domain's cell widths and ghost depth; their own
@@ -254,7 +255,7 @@ def tile(U, box, cuts):
                 nb = (i1 - i0, j1 - j0, k1 - k0)
                 bc = tuple(BC_PERIODIC if m >= ng else BC_OUTFLOW for m in nb)
                 b = box_desc(nb, ng, dx=box["dx"], bc_lo=bc)
-                W = np.zeros(state_shape(b))
+                W = np.zeros((U.shape[0],) + state_shape(b)[1:])  # gas or species
                 valid(W, b)[...] = V[:, k0:k1, j0:j1, i0:i1]
                 states.append(W)
                 boxes.append(b)

@@ -217,3 +217,19 @@ def test_species_sizes_and_rejections():
     assert call(S, Sn, 2, sws, nsws, Un=C.c_void_p((1 << 30) + 8)) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_species(None, 2, C.byref(b), None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_species(S, 9, C.byref(b), None) == hydro.HYDRO_EINVAL
+
+
+def test_batched_species_sizes_and_rejections():
+    boxes = [inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1)), inputs.box_desc((16, 4, 8), bc_lo=(1, 1, 1))]
+    assert hydro.species_workspace_bytes_boxes(boxes, 2) == sum(
+        hydro.species_workspace_bytes(b, 2) for b in boxes)
+    assert hydro.species_workspace_bytes_boxes(boxes, 0) == 0
+    L = hydro.lib()
+    p = hydro.make_params(inputs.params_desc())
+    a = C.c_void_p(1 << 30)
+    # no plan
+    assert L.advance_boxes_species(2, a, a, a, a, 2, None, C.byref(p), a, 1, None, None, a,
+                                   1 << 20, C.c_void_p(1 << 36), 1 << 20, a,
+                                   None) == hydro.HYDRO_EINVAL
+    assert L.hydro_fill_ghosts_boxes_species(2, a, 2, None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_fill_ghosts_level_species(2, a, 2, None, None) == hydro.HYDRO_EINVAL

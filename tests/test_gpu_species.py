@@ -195,3 +195,92 @@ def test_full_size_sampled(gpu, orc):
         err, bw = _cmp(gS[sl], Sn[sl])
         print("region", rlo, rhi, err, bw, flush=True)
         assert err <= TOL and bw == 1.0
+
+
+# ------------------------------------------------------------ batches and tiled levels
+
+P_, O_, R_ = inputs.BC_PERIODIC, inputs.BC_OUTFLOW, inputs.BC_REFLECT
+
+
+@pytest.mark.parametrize("lay", [
+    ((40, 24, 36), 4, ((P_, O_, R_), (P_, R_, O_)), ([0, 8, 13, 40], [0, 24], [0, 5, 20, 36])),
+    ((19, 17, 23), 3, ((O_, P_, R_), (R_, P_, R_)), ([0, 3, 19], [0, 10, 17], [0, 23])),
+])
+def test_level_species_fill_matches_oracle(gpu, lay):
+    # each species component is exchanged like the density (no sign flip):
+    # the oracle's level fill of a state whose density slot holds it
+    import torch
+    from oracle import level as olev
+    dom, ng, (bl, bh), cuts = lay
+    box = inputs.box_desc(dom, ng, bc_lo=bl, bc_hi=bh)
+    rng = np.random.default_rng(5)
+    ns = 3
+    S = np.zeros((ns,) + inputs.state_shape(box)[1:])
+    inputs.valid(S, box)[...] = rng.standard_normal(inputs.valid(S, box).shape)
+    states, boxes, lo, til = inputs.tile(S, box, cuts)
+    dev = []
+    for X, b in zip(states, boxes):
+        T = np.full_like(X, np.nan)
+        inputs.valid(T, b)[...] = inputs.valid(X, b)
+        dev.append(torch.as_tensor(T).cuda())
+    til_h = gpu.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    gpu.fill_ghosts_level_species(til_h, gpu.pointer_array(dev), ns)
+    torch.cuda.synchronize()
+    for c in range(ns):
+        as_gas = []
+        for X in states:
+            U = np.zeros((5,) + X.shape[1:])
+            U[0] = X[c]
+            as_gas.append(U)
+        want = olev.fill_ghosts_level(as_gas, boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+        for G, W in zip(dev, want):
+            assert np.array_equal(G.cpu().numpy()[c], W[0])
+    til_h.close()
+
+
+def test_batched_species_equal_single_boxes(gpu):
+    # uneven independent boxes with their own boundary kinds, one launch per
+    # stage for all of them, each box its own timestep: every box's gas and
+    # species equal its single-box advance, bit for bit
+    import torch
+    cases = [inputs.kh((24, 16, 20), seed=1), inputs.rt((16, 16, 40), seed=4),
+             inputs.sod((33, 6, 9), axis=0), inputs.smooth((17, 23, 12), seed=6)]
+    prm = cases[1][2]   # gravity on every box
+    states = [c[0] for c in cases]
+    boxes = [c[1] for c in cases]
+    S = [inputs.species(U, b, 2, seed=4 + i) for i, (U, b) in enumerate(zip(states, boxes))]
+    lev = gpu.Level(states, boxes, prm, shared_dt=False, species=S)
+    lev.run(6)
+    torch.cuda.synchronize()
+    for G, GS, U, Sb, b in zip(lev.states(), lev.species(), states, S, boxes):
+        B = gpu.SpeciesBox(U, Sb, b, prm)
+        B.run(6)
+        torch.cuda.synchronize()
+        assert np.array_equal(inputs.valid(G, b), inputs.valid(B.state(), b))
+        assert np.array_equal(inputs.valid(GS, b), inputs.valid(B.species(), b))
+
+
+def test_tiled_flattened_sedov_species_matches_oracle(gpu, orc):
+    # the 64^3 blast as 8 boxes of 32^3 tiling the domain, flattening on, two
+    # species, with both ghost exchanges: against the oracle's 64^3 box
+    import torch
+    U, box, prm = inputs.sedov(64)
+    prm = dict(prm, flatten=1)
+    S = inputs.species(U, box, 2, seed=8)
+    states, boxes, lo, til = inputs.tile(U, box, [inputs.even_cuts(64, 32)] * 3)
+    sstates, _, _, _ = inputs.tile(S, box, [inputs.even_cuts(64, 32)] * 3)
+    tiling = gpu.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    lev = gpu.Level(states, boxes, prm, shared_dt=True, tiling=tiling, species=sstates)
+    lev.run(10)
+    torch.cuda.synchronize()
+    oU, oS, oerr = _oracle_run(orc, U, S, box, prm, 10)
+    assert int(lev.err.item()) == oerr
+    WU, WS = inputs.valid(oU, box), inputs.valid(oS, box)
+    for G, GS, b, l in zip(lev.states(), lev.species(), boxes, lo):
+        n = b["n"]
+        sl = (slice(None), slice(l[2], l[2] + n[2]), slice(l[1], l[1] + n[1]),
+              slice(l[0], l[0] + n[0]))
+        assert np.array_equal(inputs.valid(G, b), WU[sl])
+        err, bw = _cmp(inputs.valid(GS, b), WS[sl])
+        assert err <= TOL and bw == 1.0
+    tiling.close()
