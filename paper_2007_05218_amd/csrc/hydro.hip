@@ -668,9 +668,9 @@ __host__ inline long long species_stage_blocks(const Geo &g, int st)
 {
     const long long nE = (long long)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
     if (st == SPS_FILL) return (g.cs + kBlock - 1) / kBlock;
-    if (st == SPS_TRACE) return (nE + kBlock - 1) / kBlock;
-    if (st == SPS_CORNER) return sp_part_blocks(nE, 6);
-    if (st == SPS_FINAL) return sp_part_blocks(nE, 3);
+    if (st == SPS_TRACE) return sp_part_blocks(nE, kSpTraceParts);
+    if (st == SPS_CORNER) return sp_part_blocks(nE, kSpCornerParts);
+    if (st == SPS_FINAL) return sp_part_blocks(nE, kSpFinalParts);
     return ((long long)g.n[0] * g.n[1] * g.n[2] + kBlock - 1) / kBlock;
 }
 

@@ -28,6 +28,9 @@
 namespace {
 
 constexpr int kMaxSpecies = 8;
+// parts per cell or face of the trace, corner and final stages (all axes,
+// one traced axis with its two flux families, one axis)
+constexpr int kSpTraceParts = 1, kSpCornerParts = 3, kSpFinalParts = 3;
 
 // Species-pass arrays (doubles, each field mf_stride long, in order):
 // 12 mass-flux fields | traced X: 6 ns (axis, high/low, species) |
@@ -146,14 +149,14 @@ __host__ inline unsigned sp_part_blocks(long long items, int nf)
     return (unsigned)((nb + 7) / 8 * 8 * nf);
 }
 
-// the (t|s) family index: (x|y) (x|z) (y|x) (y|z) (z|x) (z|y); the corner
-// stage inverts it as t = fam / 2, s = fam % 2 (+1 when >= t)
+// the (t|s) family index: (x|y) (x|z) (y|x) (y|z) (z|x) (z|y)
 __host__ __device__ constexpr int sp_fam(int t, int s) { return 2 * t + (s > t ? s - 1 : s); }
 
+// Trace stage: one thread per cell, all three axes.
 __global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A, SpBatch B)
 {
-    int x, y, z;
-    const long long t = sp_box(A, B) * kBlock + threadIdx.x;
+    int x, y, z, part;
+    const long long t = sp_part(sp_box(A, B), kSpTraceParts, part);
     if (!sp_decode(A, t, x, y, z)) return;
     const Geo &g = A.g;
     const double gm1 = A.gamma - 1.0;
@@ -166,8 +169,9 @@ __global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A, SpBatch B)
         f = ((const double *)(A.ws + ws_flat_off(g.n[0], g.n[1], g.n[2])))[t];
     const double dt = *A.dt;
     const long long stride[3] = {1, (long long)g.s[0], (long long)g.s[0] * g.s[1]};
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double un = vel(q, d);
+        const double un = d == 0 ? q.u : (d == 1 ? q.v : q.w);
         const double dtdx = dt / g.dx[d];
         for (int s = 0; s < A.ns; ++s) {
             double a[5];
@@ -183,55 +187,68 @@ __global__ void __launch_bounds__(kBlock) k_sp_trace(SpArgs A, SpBatch B)
     }
 }
 
-// Corner stage: one part per (td|sd) family.  Each thread takes one face of
-// the family: both sides' traced X corrected by dt/3 of the round-1 species
-// flux difference across their cell along sd (the round-1 species flux
-// through an sd-face is its mass flux times the traced X of the side the
-// mass leaves), then the round-2 species flux through the face.
+// Corner stage: one part per traced axis td; a thread takes the face of
+// both (td|sd) families (sd the other two axes), which share the traced
+// densities and X of the face's two cells.  For each: both sides' traced X
+// corrected by dt/3 of the round-1 species flux difference across their cell
+// along sd (the round-1 species flux through an sd-face is its mass flux
+// times the traced X of the side the mass leaves), then the round-2 species
+// flux through the face.
 __global__ void __launch_bounds__(kBlock) k_sp_corner(SpArgs A, SpBatch B)
 {
-    int p[3], fam;
-    const long long t = sp_part(sp_box(A, B), 6, fam);
+    int p[3], td;
+    const long long t = sp_part(sp_box(A, B), kSpCornerParts, td);
     if (!sp_decode(A, t, p[0], p[1], p[2])) return;
-    const int td = fam / 2, sd = (fam % 2) < td ? (fam % 2) : (fam % 2) + 1;
-    // faces of the family: td in [0, n], sd in [0, n), the third axis in [-1, n]
-    const int ptd = sel3(p, td), psd = sel3(p, sd);
-    if (ptd < 0 || psd < 0 || psd >= sel3(A.g.n, sd)) return;
-    const double fac = *A.dt / (3.0 * sel3(A.g.dx, sd));
-    const double *F1 = A.mf + sd * A.E;
-    long long ic[2], iu[2], il[2];  // the side's cell, its sd-neighbours above and below
-    double Fl[2], Fh[2], rq[2], den[2];
+    if (sel3(p, td) < 0) return;  // faces of the family: td in [0, n]
+    long long ic[2];
+    double rq[2];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         int c[3] = {p[0], p[1], p[2]};
         if (!side) c[td] -= 1;
         ic[side] = sp_idx(A, c[0], c[1], c[2]);
-        c[sd] += 1;
-        iu[side] = sp_idx(A, c[0], c[1], c[2]);
-        c[sd] -= 2;
-        il[side] = sp_idx(A, c[0], c[1], c[2]);
-        c[sd] += 1;
-        Fl[side] = F1[ic[side]];
-        Fh[side] = F1[iu[side]];
         rq[side] = sp_rho_traced(A, td, side, c[0], c[1], c[2]);
-        den[side] = rq[side] - fac * (Fh[side] - Fl[side]);
     }
-    const double F = A.mf[(3 + fam) * A.E + t];
-    for (int s = 0; s < A.ns; ++s) {
-        const double *Xq0 = A.Xt + ((td * 2 + 0) * A.ns + s) * A.E;
-        const double *Xq1 = A.Xt + ((td * 2 + 1) * A.ns + s) * A.E;
-        const double *Xh = A.Xt + ((sd * 2 + 0) * A.ns + s) * A.E;
-        const double *Xl = A.Xt + ((sd * 2 + 1) * A.ns + s) * A.E;
-        double xs[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int sd = td == 0 ? 1 + k : (td == 1 ? 2 * k : k);
+        // sd in [0, n), the third axis in [-1, n]
+        const int psd = sel3(p, sd);
+        if (psd < 0 || psd >= sel3(A.g.n, sd)) continue;
+        const double fac = *A.dt / (3.0 * sel3(A.g.dx, sd));
+        const double *F1 = A.mf + sd * A.E;
+        long long iu[2], il[2];  // each side's sd-neighbours above and below
+        double Fl[2], Fh[2], den[2];
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-            const double xq = (side ? Xq1 : Xq0)[ic[side]];
-            const double gh = Fh[side] * (Fh[side] >= 0.0 ? Xh[ic[side]] : Xl[iu[side]]);
-            const double gl = Fl[side] * (Fl[side] >= 0.0 ? Xh[il[side]] : Xl[ic[side]]);
-            const double num = rq[side] * xq - fac * (gh - gl);
-            xs[side] = den[side] > 0.0 ? num / den[side] : xq;
+            int c[3] = {p[0], p[1], p[2]};
+            if (!side) c[td] -= 1;
+            c[sd] += 1;
+            iu[side] = sp_idx(A, c[0], c[1], c[2]);
+            c[sd] -= 2;
+            il[side] = sp_idx(A, c[0], c[1], c[2]);
+            Fl[side] = F1[ic[side]];
+            Fh[side] = F1[iu[side]];
+            den[side] = rq[side] - fac * (Fh[side] - Fl[side]);
         }
-        A.G2[(fam * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xs[0] : xs[1]);
+        const int fam = sp_fam(td, sd);
+        const double F = A.mf[(3 + fam) * A.E + t];
+        for (int s = 0; s < A.ns; ++s) {
+            const double *Xq0 = A.Xt + ((td * 2 + 0) * A.ns + s) * A.E;
+            const double *Xq1 = A.Xt + ((td * 2 + 1) * A.ns + s) * A.E;
+            const double *Xh = A.Xt + ((sd * 2 + 0) * A.ns + s) * A.E;
+            const double *Xl = A.Xt + ((sd * 2 + 1) * A.ns + s) * A.E;
+            double xs[2];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const double xq = (side ? Xq1 : Xq0)[ic[side]];
+                const double gh = Fh[side] * (Fh[side] >= 0.0 ? Xh[ic[side]] : Xl[iu[side]]);
+                const double gl = Fl[side] * (Fl[side] >= 0.0 ? Xh[il[side]] : Xl[ic[side]]);
+                const double num = rq[side] * xq - fac * (gh - gl);
+                xs[side] = den[side] > 0.0 ? num / den[side] : xq;
+            }
+            A.G2[(fam * A.ns + s) * A.E + t] = F * (F >= 0.0 ? xs[0] : xs[1]);
+        }
     }
 }
 
@@ -241,7 +258,7 @@ __global__ void __launch_bounds__(kBlock) k_sp_corner(SpArgs A, SpBatch B)
 __global__ void __launch_bounds__(kBlock) k_sp_final(SpArgs A, SpBatch B)
 {
     int p[3], d;
-    const long long t = sp_part(sp_box(A, B), 3, d);
+    const long long t = sp_part(sp_box(A, B), kSpFinalParts, d);
     if (!sp_decode(A, t, p[0], p[1], p[2])) return;
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     // faces: d in [0, n], the transverse axes in [0, n)
