@@ -825,30 +825,27 @@ hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const d
                                  double *dt_next_dev, void *ws_dev, size_t ws_bytes,
                                  void *sws_dev, size_t sws_bytes, int32_t *err_dev, void *stream)
 {
-    if (!S_dev || !S_new_dev || !sws_dev || nspec < 1 || nspec > kMaxSpecies ||
-        ((uintptr_t)sws_dev & 255) || !box_valid(box))
+    // argument errors first, then the workspace sizes
+    if (!U_dev || !U_new_dev || !S_dev || !S_new_dev || !dt_dev || !ws_dev || !sws_dev ||
+        !err_dev || nspec < 1 || nspec > kMaxSpecies || !box_valid(box) || !params_valid(prm) ||
+        !flatten_ok(prm, box, 1) || ((uintptr_t)ws_dev & 255) || ((uintptr_t)sws_dev & 255))
+        return HYDRO_EINVAL;
+    if (dt_next_dev && overlaps(dt_next_dev, sizeof(double), dt_dev, sizeof(double)))
         return HYDRO_EINVAL;
     const Geo g = make_geo(box);
     const size_t sbytes = (size_t)nspec * g.cs * sizeof(double);
     const size_t ubytes = (size_t)5 * g.cs * sizeof(double);
-    // the new species must not overlap the old ones, either gas state or the
-    // species workspace; the workspace must not overlap any array
-    if (overlaps(S_dev, sbytes, S_new_dev, sbytes) || overlaps(S_new_dev, sbytes, U_dev, ubytes) ||
-        overlaps(S_new_dev, sbytes, U_new_dev, ubytes) ||
+    // no array written may overlap another array, and the species workspace
+    // overlaps none
+    if (overlaps(U_dev, ubytes, U_new_dev, ubytes) || overlaps(S_dev, sbytes, S_new_dev, sbytes) ||
+        overlaps(S_new_dev, sbytes, U_dev, ubytes) || overlaps(S_new_dev, sbytes, U_new_dev, ubytes) ||
+        overlaps(S_new_dev, sbytes, ws_dev, ws_bytes) ||
         overlaps(sws_dev, sws_bytes, S_dev, sbytes) || overlaps(sws_dev, sws_bytes, S_new_dev, sbytes) ||
         overlaps(sws_dev, sws_bytes, U_dev, ubytes) || overlaps(sws_dev, sws_bytes, U_new_dev, ubytes) ||
-        (ws_dev && overlaps(sws_dev, sws_bytes, ws_dev, ws_bytes)))
+        overlaps(sws_dev, sws_bytes, ws_dev, ws_bytes))
         return HYDRO_EINVAL;
-    if (sws_bytes < hydro_species_workspace_bytes(box, nspec)) return HYDRO_ENOWS;
-    // the gas step, with the flux kernel exporting its mass fluxes
-    if (!U_dev || !U_new_dev || !dt_dev || !ws_dev || !err_dev || !params_valid(prm) ||
-        !flatten_ok(prm, box, 1))
-        return HYDRO_EINVAL;
-    if (dt_next_dev && overlaps(dt_next_dev, sizeof(double), dt_dev, sizeof(double)))
-        return HYDRO_EINVAL;
-    if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
-    if (overlaps(U_dev, ubytes, U_new_dev, ubytes)) return HYDRO_EINVAL;
-    if (ws_bytes < box_ws_bytes(g)) return HYDRO_ENOWS;
+    if (ws_bytes < box_ws_bytes(g) || sws_bytes < hydro_species_workspace_bytes(box, nspec))
+        return HYDRO_ENOWS;
     const hipStream_t st = (hipStream_t)stream;
     long long grid[ST_COUNT];
     for (int s = 0; s < ST_COUNT; ++s) grid[s] = stage_blocks(g, s);

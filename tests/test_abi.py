@@ -215,6 +215,9 @@ def test_species_sizes_and_rejections():
     assert call(S, Sn, 2, C.c_void_p(1 << 38), nsws) == hydro.HYDRO_EINVAL          # sws over S
     assert call(S, Sn, 2, sws, nsws - 256) == hydro.HYDRO_ENOWS
     assert call(S, Sn, 2, sws, nsws, Un=C.c_void_p((1 << 30) + 8)) == hydro.HYDRO_EINVAL
+    assert call(S, ws, 2, sws, nsws) == hydro.HYDRO_EINVAL                      # S_new over ws
+    assert call(S, Sn, 2, sws, nsws, U=None) == hydro.HYDRO_EINVAL              # before sizes
+    assert call(S, Sn, 2, sws, 0, U=None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_species(None, 2, C.byref(b), None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_species(S, 9, C.byref(b), None) == hydro.HYDRO_EINVAL
 
