@@ -340,3 +340,28 @@ def test_tiled_species_level_graph_replay(gpu):
     assert int(lev.err.item()) & 7 == 0
     t1.close()
     t2.close()
+
+
+def test_species_independent_of_tile_shapes(gpu):
+    # the export's validity masks depend on the flux kernel's tile; species
+    # (and gas) results must not: 8-, 16- and 32-column tiles and several
+    # z-segment lengths, batched, all give the same bits
+    import torch
+    from paper_2007_05218_amd import autotune
+    states, boxes, prm = inputs.level(nboxes=10, seed=11)
+    prm = dict(prm, grav=(0.0, 0.0, -0.2))
+    S = [inputs.species(U, b, 2, seed=20 + i) for i, (U, b) in enumerate(zip(states, boxes))]
+    shapes = {tuple(b["n"]) for b in boxes}
+    res = []
+    for tb in [(16, 16, 16, 64), (32, 8, 8, 16), (8, 32, 32, 8), (16, 4, 8, 128)]:
+        table = {autotune.shape_key(n): tb for n in shapes}
+        lev = gpu.Level(states, boxes, prm, shared_dt=True,
+                        autotune_json=autotune.table_json(table), species=S)
+        lev.run(3)
+        torch.cuda.synchronize()
+        res.append((lev.states(), lev.species(), int(lev.err.item())))
+    for U1, S1, e1 in res[1:]:
+        assert e1 == res[0][2]
+        for a, b, sa, sb, box in zip(res[0][0], U1, res[0][1], S1, boxes):
+            assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box))
+            assert np.array_equal(inputs.valid(sa, box), inputs.valid(sb, box))
