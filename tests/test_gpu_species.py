@@ -365,3 +365,56 @@ def test_species_independent_of_tile_shapes(gpu):
         for a, b, sa, sb, box in zip(res[0][0], U1, res[0][1], S1, boxes):
             assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box))
             assert np.array_equal(inputs.valid(sa, box), inputs.valid(sb, box))
+
+
+def test_full_size_sedov_species_level_sampled(gpu, orc):
+    # the benchmark's tiled species configuration (the Sedov blast, 256^3 as
+    # 64 boxes of 64^3, two species): the tenth step from the state the GPU
+    # reached in nine, against the oracle's 256^3 box on sampled regions,
+    # several straddling box boundaries
+    import torch
+    n, bs = 256, 64
+    states, boxes, prm, lo, til = inputs.sedov_level(n, bs)
+    U0, box, _ = inputs.sedov(n)
+    cuts = [inputs.even_cuts(n, bs)] * 3
+    S0 = inputs.species(U0, box, 2, seed=8)
+    sst, _, _, _ = inputs.tile(S0, box, cuts)
+    print("sedov species level 256", flush=True)
+    tiling = gpu.Tiling(boxes, lo, til["dom"], til["bc_lo"], til["bc_hi"])
+    lev = gpu.Level(states, boxes, prm, shared_dt=True, tiling=tiling, species=sst)
+
+    def domain(parts, nc):
+        D = np.zeros((nc, n, n, n))
+        for G, b, l in zip(parts, boxes, lo):
+            m = b["n"]
+            D[:, l[2]:l[2] + m[2], l[1]:l[1] + m[1], l[0]:l[0] + m[0]] = inputs.valid(G, b)
+        return D
+
+    lev.run(9)
+    torch.cuda.synchronize()
+    U, S = U0.copy(), S0.copy()
+    inputs.valid(U, box)[...] = domain(lev.states(), 5)
+    inputs.valid(S, box)[...] = domain(lev.species(), 2)
+    lev.step()
+    torch.cuda.synchronize()
+    gdt = lev.dt_min.item()
+    DU, DS = domain(lev.states(), 5), domain(lev.species(), 2)
+    del lev
+    tiling.close()
+    torch.cuda.empty_cache()
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    orc.fill_ghosts(U, ob)
+    orc.fill_ghosts_species(S, ob)
+    assert orc.estimate_dt(U, ob, op) == gdt
+    ng = box["ng"]
+    Un, Sn = np.empty_like(U), np.empty_like(S)
+    for rlo, rhi in [((124, 124, 124), (132, 132, 132)), ((60, 120, 126), (68, 128, 130)),
+                     ((0, 0, 0), (4, 4, 4)), ((126, 62, 60), (130, 66, 68))]:
+        orc.advance_region_species(U, Un, S, Sn, ob, op, gdt, rlo, rhi)
+        sl = (slice(ng + rlo[2], ng + rhi[2]), slice(ng + rlo[1], ng + rhi[1]),
+              slice(ng + rlo[0], ng + rhi[0]))
+        dl = (slice(rlo[2], rhi[2]), slice(rlo[1], rhi[1]), slice(rlo[0], rhi[0]))
+        assert np.array_equal(DU[(slice(None),) + dl], Un[(slice(None),) + sl])
+        err, bw = _cmp(DS[(slice(None),) + dl], Sn[(slice(None),) + sl])
+        print("region", rlo, rhi, err, bw, flush=True)
+        assert err <= TOL and bw == 1.0
