@@ -418,3 +418,20 @@ def test_full_size_sedov_species_level_sampled(gpu, orc):
         err, bw = _cmp(DS[(slice(None),) + dl], Sn[(slice(None),) + sl])
         print("region", rlo, rhi, err, bw, flush=True)
         assert err <= TOL and bw == 1.0
+
+
+def test_nonfinite_species_flagged_like_the_oracle(gpu, orc):
+    U, box, prm = inputs.kh(20, seed=2)
+    S = inputs.species(U, box, 2, seed=1)
+    ng = box["ng"]
+    S[1, ng + 5, ng + 6, ng + 7] = np.nan
+    gU, gS, gerr = _gpu_run(gpu, U, S, box, prm, 1)
+    oU, oS, oerr = _oracle_run(orc, U, S, box, prm, 1)
+    assert gerr == oerr and gerr & gpu.ERR_NONFINITE
+    V = inputs.valid
+    assert np.array_equal(V(gU, box), V(oU, box))
+    g0, o0 = V(gS, box)[0], V(oS, box)[0]
+    assert np.array_equal(g0, o0)
+    g1, o1 = V(gS, box)[1], V(oS, box)[1]
+    assert np.array_equal(np.isnan(g1), np.isnan(o1))
+    assert np.array_equal(g1[~np.isnan(g1)], o1[~np.isnan(o1)])

@@ -240,3 +240,17 @@ def test_invalid_species_arguments_rejected(orc):
         orc.fill_ghosts_species(S, ob)
     with pytest.raises(ValueError):
         orc.advance_box_species(U, U.copy(), S, S.copy(), ob, op, 1e-3)
+
+
+def test_nonfinite_species_flagged_gas_untouched(orc):
+    U, box, prm = inputs.kh(12, seed=2)
+    S = inputs.species(U, box, 2, seed=1)
+    ng = box["ng"]
+    S[1, ng + 5, ng + 6, ng + 7] = np.nan
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    Ua, Sa, dta, ea = orc.step_species(U, S, ob, op)
+    Ub, dtb, eb = orc.step(U, ob, op)
+    assert ea & orc.ERR_NONFINITE and not eb & orc.ERR_NONFINITE
+    assert np.array_equal(inputs.valid(Ua, box), inputs.valid(Ub, box))
+    # the other species is unaffected
+    assert np.all(np.isfinite(inputs.valid(Sa, box)[0]))
