@@ -435,3 +435,21 @@ def test_nonfinite_species_flagged_like_the_oracle(gpu, orc):
     g1, o1 = V(gS, box)[1], V(oS, box)[1]
     assert np.array_equal(np.isnan(g1), np.isnan(o1))
     assert np.array_equal(g1[~np.isnan(g1)], o1[~np.isnan(o1)])
+
+
+def test_species_totals_conserved_full_size(gpu):
+    # KH 256^3 is periodic on every axis: each species' total over the valid
+    # cells stays what it was (to rounding of the sums), at the benchmark's size
+    import torch
+    U, box, prm = inputs.kh(256, seed=1)
+    S = inputs.species(U, box, 2, seed=3)
+    B = gpu.SpeciesBox(U, S, box, prm)
+    n, ng = box["n"], box["ng"]
+    v = (slice(None), slice(ng, ng + n[2]), slice(ng, ng + n[1]), slice(ng, ng + n[0]))
+    tot0 = B.S[v].sum(dim=(1, 2, 3))
+    B.run(10)
+    torch.cuda.synchronize()
+    tot1 = B.S[v].sum(dim=(1, 2, 3))
+    rel = ((tot1 - tot0).abs() / tot0.abs()).max().item()
+    print("species totals relative change %.3e" % rel, flush=True)
+    assert rel < 1e-12 and int(B.err.item()) & 7 == 0
