@@ -601,6 +601,11 @@ static int accept_state(const double V[5], const double q[5], double gm1,
     return 0;
 }
 
+int orc_accept_state(const double V[5], const double q[5], double gamma, double out[5])
+{
+    return accept_state(V, q, gamma - 1.0, out);
+}
+
 /* ------------------------------------------------------------------ */
 /* one step on an output region                                        */
 /* ------------------------------------------------------------------ */

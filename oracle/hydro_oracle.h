@@ -145,6 +145,14 @@ void orc_hllc(const double qL[5], const double qR[5], int d, double gamma,
 void orc_prim_of_cons(const double U[5], double gamma, double q[5]);
 void orc_cons_of_prim(const double q[5], double gamma, double U[5]);
 
+/* The rule that accepts or rejects a transverse-corrected state: out = the
+ * primitive form (rho,u,v,w,p) of the corrected conserved state V when its
+ * density and pressure are both positive, else out = q (the uncorrected
+ * primitive state) and the return value is ORC_ERR_FALLBACK (0 otherwise).
+ * The corner (dt/3) and final (dt/2) stages of the step apply exactly this
+ * function to every corrected face state. */
+int orc_accept_state(const double V[5], const double q[5], double gamma, double out[5]);
+
 /* Number of OpenMP threads the oracle runs on (1 when built without it). */
 int orc_num_threads(void);
 

@@ -83,6 +83,8 @@ def _load(path):
         L.orc_prim_of_cons.argtypes = [dp, C.c_double, dp]
         L.orc_cons_of_prim.argtypes = [dp, C.c_double, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_accept_state.argtypes = [dp, dp, C.c_double, dp]
+        L.orc_accept_state.restype = C.c_int
         for f in ("orc_ppm_parabola", "orc_ppm_parabola_flat", "orc_ppm_integrals", "orc_trace", "orc_hllc",
                   "orc_prim_of_cons", "orc_cons_of_prim"):
             getattr(L, f).restype = None
@@ -273,6 +275,17 @@ def cons_of_prim(q, gamma):
     U = np.zeros(5)
     lib().orc_cons_of_prim(_dp(a), gamma, _dp(U))
     return U
+
+
+def accept_state(V, q, gamma):
+    """The corrected-state rule: returns (state, flag), state the primitive
+    form of the conserved V, or q with flag ERR_FALLBACK when V's density or
+    pressure is not positive."""
+    a = np.ascontiguousarray(V, dtype=np.float64)
+    b = np.ascontiguousarray(q, dtype=np.float64)
+    out = np.zeros(5)
+    flag = lib().orc_accept_state(_dp(a), _dp(b), gamma, _dp(out))
+    return out, flag
 
 
 def num_threads():

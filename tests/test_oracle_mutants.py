@@ -1,8 +1,8 @@
 """The pins catch plausible mistakes: each mutant below is the oracle's source
 with one deliberate error (a flipped sign, a dropped term, a wrong constant
 or operand), compiled on the CPU; the battery of pins of
-test_oracle_pieces.py / test_oracle_scheme.py / test_oracle_flatten.py /
-test_oracle_species.py is run against it and at least
+test_oracle_pieces.py / test_oracle_scheme.py / test_oracle_fallback.py /
+test_oracle_flatten.py / test_oracle_species.py is run against it and at least
 one pin must fail.  Nothing here touches a GPU."""
 import os
 import subprocess
@@ -10,6 +10,7 @@ import tempfile
 
 import pytest
 
+import test_oracle_fallback as FB
 import test_oracle_flatten as F
 import test_oracle_pieces as P
 import test_oracle_scheme as S
@@ -88,6 +89,30 @@ MUTANTS = {
     "species update y-difference sign": (
         "du = du + dtdx[1] * (fat(&G3[1], py)[sp] - fat(&G3[1], p)[sp]);",
         "du = du - dtdx[1] * (fat(&G3[1], py)[sp] - fat(&G3[1], p)[sp]);"),
+    "fallback rejects only negative density": (
+        "if (rho <= 0.0 || p <= 0.0) {",
+        "if (rho < 0.0 || p <= 0.0) {"),
+    "fallback tests the pressure only": (
+        "if (rho <= 0.0 || p <= 0.0) {",
+        "if (p <= 0.0) {"),
+    "fallback flag dropped": (
+        "return ORC_ERR_FALLBACK;",
+        "return 0;"),
+    "corner fallback keeps the corrected state": (
+        "err |= accept_state(V, q, gm1, qc[side]);",
+        "err |= accept_state(V, V, gm1, qc[side]);"),
+    "update pressure bit dropped": (
+        "if (qn[4] <= 0.0) err |= ORC_ERR_P;",
+        ""),
+    "update density bit strict": (
+        "if (Us[0] <= 0.0) err |= ORC_ERR_RHO;",
+        "if (Us[0] < 0.0) err |= ORC_ERR_RHO;"),
+    "species corner density reset dropped": (
+        "xc[side][sp] = den > 0.0 ? num / den : xq[sp];",
+        "xc[side][sp] = num / den;"),
+    "species final density reset dropped": (
+        "xf[side][sp] = den > 0.0 ? num / den : xq[sp];",
+        "xf[side][sp] = num / den;"),
     "flattening steepness threshold": (
         "double chi = mn(1.0, mx(0.0, FL_W2 * (z - FL_W1)));",
         "double chi = mn(1.0, mx(0.0, FL_W2 * (z - 0.5)));"),
@@ -105,6 +130,12 @@ BATTERY = [
     ("HLLC consistency", lambda o: P.test_hllc_consistency(o)),
     ("HLLC mirror", lambda o: P.test_hllc_mirror_symmetry(o)),
     ("HLLC contact", lambda o: (P.test_hllc_stationary_contact(o), P.test_hllc_moving_contact_is_upwind(o))),
+    ("corrected-state rule", lambda o: ([FB.test_rejected_state_keeps_the_uncorrected_one(o, v, w)
+                                         for v, w in FB.REJECTED],
+                                        FB.test_accepted_state_is_its_primitive_form(o))),
+    ("update bits closed form", lambda o: [FB.test_update_error_bits_on_expansion_closed_form(o, 1, s, b)
+                                           for s, b in FB.EXPANSION_CASES]),
+    ("non-finite reach", lambda o: FB.test_nonfinite_input_raises_bit_1_within_the_stencil_reach(o)),
     ("uniform state", lambda o: S.test_uniform_state_preserved_bitwise(o)),
     ("free fall", lambda o: S.test_free_fall_gravity_closed_form(o)),
     ("Sod permutation", lambda o: S.test_sod_axis_permutation_bitwise(o, 2)),
@@ -122,6 +153,8 @@ BATTERY = [
     ("flattening toward the mean", lambda o: F.test_flattening_limits_the_parabola_toward_the_mean(o)),
     ("full flattening first order", lambda o: F.test_full_flattening_is_first_order(o)),
     ("strong shock marked", lambda o: F.test_coefficient_marks_a_strong_shock_only(o)),
+    ("first-order CTU", lambda o: [FB.test_first_step_on_piecewise_constant_data_is_first_order_ctu(o, *c)
+                                   for c in FB.CTU_CASES]),
     ("species unit fraction", lambda o: [SP.test_unit_fraction_is_the_density_bitwise(o, c)
                                          for c in ("kh", "rt")]),
     ("species 1-D advection", lambda o: [SP.test_uniform_flow_is_1d_ppm_advection(o, a, u)

@@ -185,7 +185,12 @@ def test_conservation_periodic(orc, make):
     elif make == "smooth":
         U, box, prm = inputs.smooth((16, 32, 24), seed=11)
     else:
-        U, box, prm = inputs.kh(16, seed=5)
+        # the Rayleigh-Taylor layers on a box periodic along every axis and
+        # without gravity (a source of momentum and energy): a sharp density
+        # interface in a gas at rest
+        U, box, prm = inputs.rt((16, 12, 20), seed=5)
+        box = dict(box, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0))
+        prm = dict(prm, grav=(0.0, 0.0, 0.0))
     ob, op = _obox(orc, box), _oprm(orc, prm)
     V0 = inputs.valid(U, box).copy()
     R, _, err = orc.run(U, ob, op, 20)
