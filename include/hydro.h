@@ -123,8 +123,8 @@ hydro_status estimate_dt(double *U_dev, const hydro_box *box, const hydro_params
  * cells of U_new_dev from U_dev, whose ghosts must be filled (estimate_dt
  * does it).  Ghost cells of U_new_dev are not written.  U_new_dev must not
  * overlap U_dev.  ws_dev must hold hydro_workspace_bytes(box, 1) bytes
- * (HYDRO_ENOWS otherwise), aligned to 256 bytes; its contents on entry do
- * not matter.  Error bits go to *err_dev (not cleared by the call).
+ * (HYDRO_ENOWS otherwise), aligned to 256 bytes, overlapping neither state
+ * (HYDRO_EINVAL); its contents on entry do not matter.  Error bits go to *err_dev (not cleared by the call).
  * If dt_next_dev is not NULL it receives the CFL timestep of the new state,
  * bitwise what estimate_dt gives for U_new_dev (its valid cells decide it),
  * reduced in the update's epilogue instead of a separate pass over U_new:
@@ -163,8 +163,8 @@ hydro_status hydro_fill_ghosts_species(double *S_dev, int nspec, const hydro_box
  * differences, the traced X kept where that density is not positive.
  * sws_dev (sws_bytes >= hydro_species_workspace_bytes(box, nspec), else
  * HYDRO_ENOWS; 256-byte aligned) is scratch whose contents on entry do not
- * matter.  S_new_dev must not overlap S_dev, the gas states or the
- * workspaces, nor the species workspace any array (HYDRO_EINVAL).  A
+ * matter.  No array written (U_new_dev, S_new_dev, ws_dev, sws_dev) may
+ * overlap another of the arrays passed (HYDRO_EINVAL).  A
  * non-finite new partial density raises error bit 1. */
 hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const double *S_dev,
                                  double *S_new_dev, int nspec, const hydro_box *box,
@@ -278,6 +278,37 @@ hydro_status hydro_fill_ghosts_level_species(int nb, double *const *S_ptrs_dev, 
  * an opaque handle.  HYDRO_EINVAL for an invalid box or table. */
 hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,
                                void **plan);
+
+/* A plan whose list of boxes changes while it is in use (the serving loop
+ * of Sec. III's device-resident data: runs join and leave a batch while
+ * their states stay on the GPU).  hydro_plan_create_capacity makes an empty
+ * plan for lists of up to `capacity` boxes (1 <= capacity <= 2^20), with
+ * the tile table as in hydro_plan_create; it allocates the plan's device
+ * buffer and a few pinned host staging buffers once.  Until its first
+ * update the plan has no boxes and every batched call on it is
+ * HYDRO_EINVAL.  HYDRO_EHIP if an allocation fails. */
+hydro_status hydro_plan_create_capacity(int capacity, const char *autotune_json, void **plan);
+
+/* Replace the plan's list by boxes[0..nb) (1 <= nb <= capacity; the host
+ * array is read during the call only).  The new work lists are written to a
+ * pinned staging buffer and copied to the plan's device buffer with an
+ * asynchronous copy on `stream`, so batched calls enqueued afterwards on
+ * that stream use the new list and calls enqueued before it the old one:
+ * every call using the plan must be on that one stream.  The host blocks
+ * only when all staging buffers still wait for earlier copies (the copy
+ * enqueued four updates back).  No device memory is allocated.  Box b of the
+ * new list is the b-th pointer of the pointer arrays the batched calls take;
+ * the workspace they need becomes hydro_plan_workspace_bytes(plan).
+ * HYDRO_EINVAL (plan unchanged) for an invalid box, nb out of range, or a
+ * plan made by hydro_plan_create. */
+hydro_status hydro_plan_update(void *plan, const hydro_box *boxes, int nb, void *stream);
+
+/* Boxes in the plan's current list (0 for an empty capacity plan, -1 for
+ * NULL), and the workspace in bytes that the batched calls need for it. */
+int hydro_plan_boxes(const void *plan);
+size_t hydro_plan_workspace_bytes(const void *plan);
+
+/* Release a plan (waiting for its pending staging copies). */
 void hydro_plan_destroy(void *plan);
 
 /* Profiling aid.  The library's kernels form hydro_stage_count() stage

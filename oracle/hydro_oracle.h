@@ -156,6 +156,10 @@ int orc_accept_state(const double V[5], const double q[5], double gamma, double 
 /* Number of OpenMP threads the oracle runs on (1 when built without it). */
 int orc_num_threads(void);
 
+/* Threads of the oracle's later calls made from the calling host thread
+ * (several host threads may each advance their own boxes at once). */
+void orc_set_num_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif

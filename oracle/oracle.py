@@ -83,6 +83,8 @@ def _load(path):
         L.orc_prim_of_cons.argtypes = [dp, C.c_double, dp]
         L.orc_cons_of_prim.argtypes = [dp, C.c_double, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         L.orc_accept_state.argtypes = [dp, dp, C.c_double, dp]
         L.orc_accept_state.restype = C.c_int
         for f in ("orc_ppm_parabola", "orc_ppm_parabola_flat", "orc_ppm_integrals", "orc_trace", "orc_hllc",
@@ -290,6 +292,41 @@ def accept_state(V, q, gamma):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of the later oracle calls made from this host thread."""
+    lib().orc_set_num_threads(int(n))
+
+
+def level_step(states, boxes, prm, workers=8):
+    """One step of independent boxes with the level-wide timestep: ghost fill
+    and CFL timestep of every box, their minimum, the advance of every box by
+    it.  Several boxes at once on a pool of host threads (each oracle call
+    releases the GIL), the OpenMP threads shared among them.  Returns (new
+    states, the timestep, error bits); the states passed get their ghosts
+    filled."""
+    from concurrent.futures import ThreadPoolExecutor
+    per = max(1, max(1, num_threads()) // workers)
+
+    def dt_of(i):
+        set_num_threads(per)
+        fill_ghosts(states[i], boxes[i])
+        return estimate_dt(states[i], boxes[i], prm)
+
+    with ThreadPoolExecutor(workers) as pool:
+        dt = min(pool.map(dt_of, range(len(states))))
+
+        def one(i):
+            set_num_threads(per)
+            Un = states[i].copy()
+            return Un, advance_box(states[i], Un, boxes[i], prm, dt)
+
+        res = list(pool.map(one, range(len(states))))
+    err = 0
+    for _, e in res:
+        err |= e
+    return [r[0] for r in res], dt, err
 
 
 # stage -> (mark index, work units of the stage per cell-update of an

@@ -674,25 +674,184 @@ __host__ inline long long species_stage_blocks(const Geo &g, int st)
     return ((long long)g.n[0] * g.n[1] * g.n[2] + kBlock - 1) / kBlock;
 }
 
+// A plan: the per-stage work lists of a list of boxes, in one device
+// buffer.  The buffer is laid out for `cap` boxes (fixed offsets), so a plan
+// made with a capacity can be refilled for any list of up to cap boxes by
+// one asynchronous copy from a pinned staging buffer, ordered on the stream
+// with the launches that use it.
+constexpr int kMaxPlanBoxes = 1 << 20;
+constexpr int kPlanStaging = 4;  // pinned staging buffers of a capacity plan
+
 struct Plan {
-    int nb;
+    int nb = 0;   // boxes in the current list
+    int cap = 0;  // boxes the device buffer is laid out for
+    std::vector<TileRule> rules;
     std::vector<hydro_box> boxes;
     std::vector<Geo> geos;
-    size_t ws_bytes;
-    long long grid[ST_COUNT];  // total blocks per stage
-    long long sp_grid[SPS_COUNT];
-    long long etot;            // sum of the boxes' field strides (species arrays)
-    // device buffer: [Geo nb][long long wsoff nb][int order ST_COUNT x nb]
-    // [unsigned pre ST_COUNT x (nb+1)][unsigned species pre SPS_COUNT x (nb+1)]
-    // [long long epre nb+1]
-    void *dev;
-    const Geo *geos_dev;
-    const long long *wsoff_dev;
-    const int *order_dev[ST_COUNT];
-    const unsigned *pre_dev[ST_COUNT];
-    const unsigned *sp_pre_dev[SPS_COUNT];
-    const long long *epre_dev;
+    size_t ws_bytes = 0;
+    long long grid[ST_COUNT] = {};  // total blocks per stage
+    long long sp_grid[SPS_COUNT] = {};
+    long long etot = 0;  // sum of the boxes' field strides (species arrays)
+    // device buffer, for cap boxes: [Geo cap][long long wsoff cap]
+    // [int order ST_COUNT x cap][unsigned pre ST_COUNT x (cap+1)]
+    // [unsigned species pre SPS_COUNT x (cap+1)][long long epre cap+1]
+    std::vector<char> image;  // its host image for the current list
+    size_t off_w = 0, off_o = 0, off_p = 0, off_s = 0, off_e = 0, bytes = 0;
+    void *dev = nullptr;
+    const Geo *geos_dev = nullptr;
+    const long long *wsoff_dev = nullptr;
+    const int *order_dev[ST_COUNT] = {};
+    const unsigned *pre_dev[ST_COUNT] = {};
+    const unsigned *sp_pre_dev[SPS_COUNT] = {};
+    const long long *epre_dev = nullptr;
+    // capacity plans: pinned staging buffers and the event of each one's last copy
+    int nstage = 0, next_stage = 0;
+    void *stage[kPlanStaging] = {};
+    hipEvent_t stage_ev[kPlanStaging] = {};
+    int stage_used[kPlanStaging] = {};
 };
+
+inline size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+// capacity, tile table and buffer layout
+hydro_status plan_init(Plan *P, int cap, const char *autotune_json)
+{
+    if (autotune_json && !parse_tiles(autotune_json, P->rules)) return HYDRO_EINVAL;
+    P->cap = cap;
+    const size_t C = (size_t)cap;
+    P->off_w = round256(sizeof(Geo) * C);
+    P->off_o = P->off_w + round256(sizeof(long long) * C);
+    P->off_p = P->off_o + round256(sizeof(int) * ST_COUNT * C);
+    P->off_s = P->off_p + round256(sizeof(unsigned) * ST_COUNT * (C + 1));
+    P->off_e = P->off_s + round256(sizeof(unsigned) * SPS_COUNT * (C + 1));
+    P->bytes = P->off_e + sizeof(long long) * (C + 1);
+    return HYDRO_OK;
+}
+
+// validate the boxes and build the work lists and the buffer's host image
+hydro_status plan_build(Plan *P, const hydro_box *boxes, int nb)
+{
+    if (nb < 1 || nb > P->cap) return HYDRO_EINVAL;
+    if (P->bytes == 0) plan_init(P, P->cap, nullptr);
+    const size_t C = (size_t)P->cap;
+    P->nb = nb;
+    P->boxes.assign(boxes, boxes + nb);
+    P->geos.clear();
+    P->ws_bytes = 0;
+    P->image.assign(P->bytes, 0);
+    char *img = P->image.data();
+    long long *wsoff = (long long *)(img + P->off_w);
+    for (int b = 0; b < nb; ++b) {
+        if (!box_valid(&boxes[b])) return HYDRO_EINVAL;
+        Geo g = make_geo(&boxes[b]);
+        for (const TileRule &r : P->rules)
+            if (r.n[0] == g.n[0] && r.n[1] == g.n[1] && r.n[2] == g.n[2]) {
+                if (r.t[0] != 0) {
+                    g.tbx1 = r.t[0];
+                    g.tzs1 = r.t[1];
+                }
+                if (r.t[2] != 0) {
+                    g.tbx2 = r.t[2];
+                    g.tzs2 = r.t[3];
+                }
+            }
+        P->geos.push_back(g);
+        wsoff[b] = (long long)(P->ws_bytes / sizeof(double));
+        P->ws_bytes += box_ws_bytes(g);
+    }
+    memcpy(img, P->geos.data(), sizeof(Geo) * nb);
+    // Work lists: for the marching kernels, boxes in order of decreasing
+    // block length (the z-planes one block marches over), so the longest
+    // blocks start first and short ones fill the end of the launch; the
+    // other stages take the boxes in the given order.
+    int *order = (int *)(img + P->off_o);
+    unsigned *pre = (unsigned *)(img + P->off_p);
+    for (int s = 0; s < ST_COUNT; ++s) {
+        int *o = order + (size_t)s * C;
+        for (int b = 0; b < nb; ++b) o[b] = b;
+        auto zlen = [&](int b) {
+            const Geo &g = P->geos[b];
+            if (s == ST_FLUX) return g.tzs2 < g.n[2] ? g.tzs2 : g.n[2];
+            if (s == ST_TRACE) return g.tzs1 < g.n[2] + 2 ? g.tzs1 : g.n[2] + 2;
+            return 0;
+        };
+        std::stable_sort(o, o + nb, [&](int a, int b) { return zlen(a) > zlen(b); });
+        unsigned *ps = pre + (size_t)s * (C + 1);
+        unsigned long long acc = 0;
+        for (int i = 0; i < nb; ++i) {
+            ps[i] = (unsigned)acc;
+            acc += (unsigned long long)stage_blocks(P->geos[o[i]], s);
+        }
+        if (acc >= (1ULL << 31)) return HYDRO_EINVAL;
+        ps[nb] = (unsigned)acc;
+        P->grid[s] = (long long)acc;
+    }
+    // the species stages take the boxes in the given order
+    unsigned *spre = (unsigned *)(img + P->off_s);
+    for (int s = 0; s < SPS_COUNT; ++s) {
+        unsigned *ps = spre + (size_t)s * (C + 1);
+        unsigned long long acc = 0;
+        for (int b = 0; b < nb; ++b) {
+            ps[b] = (unsigned)acc;
+            acc += (unsigned long long)species_stage_blocks(P->geos[b], s);
+        }
+        if (acc >= (1ULL << 31)) return HYDRO_EINVAL;
+        ps[nb] = (unsigned)acc;
+        P->sp_grid[s] = (long long)acc;
+    }
+    long long *epre = (long long *)(img + P->off_e);
+    epre[0] = 0;
+    for (int b = 0; b < nb; ++b)
+        epre[b + 1] = epre[b] + mf_stride(P->geos[b].n[0], P->geos[b].n[1], P->geos[b].n[2]);
+    P->etot = epre[nb];
+    return HYDRO_OK;
+}
+
+// the device buffer (and, for a capacity plan, nstage pinned staging buffers)
+hydro_status plan_alloc(Plan *P, int nstage)
+{
+    if (hipMalloc(&P->dev, P->bytes) != hipSuccess) {
+        P->dev = nullptr;
+        return HYDRO_EHIP;
+    }
+    char *base = (char *)P->dev;
+    const size_t C = (size_t)P->cap;
+    P->geos_dev = (const Geo *)base;
+    P->wsoff_dev = (const long long *)(base + P->off_w);
+    for (int s = 0; s < ST_COUNT; ++s) {
+        P->order_dev[s] = (const int *)(base + P->off_o) + (size_t)s * C;
+        P->pre_dev[s] = (const unsigned *)(base + P->off_p) + (size_t)s * (C + 1);
+    }
+    for (int s = 0; s < SPS_COUNT; ++s)
+        P->sp_pre_dev[s] = (const unsigned *)(base + P->off_s) + (size_t)s * (C + 1);
+    P->epre_dev = (const long long *)(base + P->off_e);
+    for (int k = 0; k < nstage; ++k) {
+        if (hipHostMalloc(&P->stage[k], P->bytes, hipHostMallocDefault) != hipSuccess) {
+            P->stage[k] = nullptr;
+            return HYDRO_EHIP;
+        }
+        if (hipEventCreateWithFlags(&P->stage_ev[k], hipEventDisableTiming) != hipSuccess) {
+            P->stage_ev[k] = nullptr;
+            return HYDRO_EHIP;
+        }
+        P->nstage = k + 1;
+    }
+    return HYDRO_OK;
+}
+
+// release everything a plan holds (waits for its pending copies first)
+void plan_free(Plan *P)
+{
+    for (int k = 0; k < kPlanStaging; ++k) {
+        if (P->stage_ev[k]) {
+            if (P->stage_used[k]) (void)hipEventSynchronize(P->stage_ev[k]);
+            (void)hipEventDestroy(P->stage_ev[k]);
+        }
+        if (P->stage[k]) (void)hipHostFree(P->stage[k]);
+    }
+    if (P->dev) (void)hipFree(P->dev);
+    delete P;
+}
 
 // the species pass (trace, corner, final, update) of one box (B.nb == 0)
 // or a batch (B with the plan's species prefixes)
@@ -772,22 +931,33 @@ static bool overlaps(const void *a, size_t na, const void *b, size_t nb)
     return a0 < b0 + nb && b0 < a0 + na;
 }
 
+// argument checks of advance_box that do not involve the workspace
+static hydro_status advance_box_args(const double *U_dev, double *U_new_dev,
+                                     const hydro_box *box, const hydro_params *prm,
+                                     const double *dt_dev, double *dt_next_dev, int32_t *err_dev)
+{
+    if (!U_dev || !U_new_dev || !dt_dev || !err_dev || !box_valid(box) || !params_valid(prm) ||
+        !flatten_ok(prm, box, 1))
+        return HYDRO_EINVAL;
+    if (dt_next_dev && overlaps(dt_next_dev, sizeof(double), dt_dev, sizeof(double)))
+        return HYDRO_EINVAL;
+    const size_t ub = 5 * (size_t)make_geo(box).cs * sizeof(double);
+    if (overlaps(U_dev, ub, U_new_dev, ub)) return HYDRO_EINVAL;  // the new state vs the old
+    return HYDRO_OK;
+}
+
 hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box *box,
                          const hydro_params *prm, const double *dt_dev, double *dt_next_dev,
                          void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream)
 {
-    if (!U_dev || !U_new_dev || !dt_dev || !ws_dev || !err_dev || !box_valid(box) ||
-        !params_valid(prm) || !flatten_ok(prm, box, 1))
-        return HYDRO_EINVAL;
-    if (dt_next_dev && overlaps(dt_next_dev, sizeof(double), dt_dev, sizeof(double)))
-        return HYDRO_EINVAL;
-    if (((uintptr_t)ws_dev) & 255) return HYDRO_EINVAL;
+    hydro_status rc = advance_box_args(U_dev, U_new_dev, box, prm, dt_dev, dt_next_dev, err_dev);
+    if (rc != HYDRO_OK) return rc;
+    if (!ws_dev || (((uintptr_t)ws_dev) & 255)) return HYDRO_EINVAL;
     Geo g = make_geo(box);
-    {  // the new state must not overlap the old one
-        uintptr_t a0 = (uintptr_t)U_dev, a1 = a0 + 5 * g.cs * sizeof(double);
-        uintptr_t b0 = (uintptr_t)U_new_dev, b1 = b0 + 5 * g.cs * sizeof(double);
-        if (a0 < b1 && b0 < a1) return HYDRO_EINVAL;
-    }
+    const size_t ub = 5 * (size_t)g.cs * sizeof(double);
+    // the workspace must not overlap the states it is read and written with
+    if (overlaps(ws_dev, ws_bytes, U_dev, ub) || overlaps(ws_dev, ws_bytes, U_new_dev, ub))
+        return HYDRO_EINVAL;
     if (ws_bytes < box_ws_bytes(g)) return HYDRO_ENOWS;
     long long grid[ST_COUNT];
     for (int s = 0; s < ST_COUNT; ++s) grid[s] = stage_blocks(g, s);
@@ -835,11 +1005,13 @@ hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const d
     const Geo g = make_geo(box);
     const size_t sbytes = (size_t)nspec * g.cs * sizeof(double);
     const size_t ubytes = (size_t)5 * g.cs * sizeof(double);
-    // no array written may overlap another array, and the species workspace
-    // overlaps none
+    // no array written (U_new, S_new, both workspaces) may overlap another
+    // array
     if (overlaps(U_dev, ubytes, U_new_dev, ubytes) || overlaps(S_dev, sbytes, S_new_dev, sbytes) ||
         overlaps(S_new_dev, sbytes, U_dev, ubytes) || overlaps(S_new_dev, sbytes, U_new_dev, ubytes) ||
-        overlaps(S_new_dev, sbytes, ws_dev, ws_bytes) ||
+        overlaps(S_new_dev, sbytes, ws_dev, ws_bytes) || overlaps(S_dev, sbytes, U_new_dev, ubytes) ||
+        overlaps(ws_dev, ws_bytes, S_dev, sbytes) || overlaps(ws_dev, ws_bytes, U_dev, ubytes) ||
+        overlaps(ws_dev, ws_bytes, U_new_dev, ubytes) ||
         overlaps(sws_dev, sws_bytes, S_dev, sbytes) || overlaps(sws_dev, sws_bytes, S_new_dev, sbytes) ||
         overlaps(sws_dev, sws_bytes, U_dev, ubytes) || overlaps(sws_dev, sws_bytes, U_new_dev, ubytes) ||
         overlaps(sws_dev, sws_bytes, ws_dev, ws_bytes))
@@ -884,125 +1056,89 @@ hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autot
 {
     if (!boxes || nb < 1 || !plan_out) return HYDRO_EINVAL;
     *plan_out = nullptr;
-    std::vector<TileRule> rules;
-    if (autotune_json && !parse_tiles(autotune_json, rules)) return HYDRO_EINVAL;
     Plan *P = new (std::nothrow) Plan();
     if (!P) return HYDRO_EINVAL;
-    P->nb = nb;
-    P->boxes.assign(boxes, boxes + nb);
-    P->ws_bytes = 0;
-    std::vector<long long> wsoff(nb);
-    std::vector<unsigned> pre((size_t)ST_COUNT * (nb + 1));
-    for (int b = 0; b < nb; ++b) {
-        if (!box_valid(&boxes[b])) {
-            delete P;
-            return HYDRO_EINVAL;
-        }
-        Geo g = make_geo(&boxes[b]);
-        for (const TileRule &r : rules)
-            if (r.n[0] == g.n[0] && r.n[1] == g.n[1] && r.n[2] == g.n[2]) {
-                if (r.t[0] != 0) {
-                    g.tbx1 = r.t[0];
-                    g.tzs1 = r.t[1];
-                }
-                if (r.t[2] != 0) {
-                    g.tbx2 = r.t[2];
-                    g.tzs2 = r.t[3];
-                }
-            }
-        P->geos.push_back(g);
-        wsoff[b] = (long long)(P->ws_bytes / sizeof(double));
-        P->ws_bytes += box_ws_bytes(g);
+    hydro_status rc = plan_init(P, nb, autotune_json);
+    if (rc == HYDRO_OK) rc = plan_build(P, boxes, nb);
+    if (rc == HYDRO_OK) rc = plan_alloc(P, 0);
+    // a fixed plan is set up once: a synchronous upload
+    if (rc == HYDRO_OK && hipMemcpy(P->dev, P->image.data(), P->image.size(),
+                                    hipMemcpyHostToDevice) != hipSuccess)
+        rc = HYDRO_EHIP;
+    if (rc != HYDRO_OK) {
+        plan_free(P);
+        return rc;
     }
-    // Work lists: for the marching kernels, boxes in order of decreasing
-    // block length (the z-planes one block marches over), so the longest
-    // blocks start first and short ones fill the end of the launch; the
-    // other stages take the boxes in the given order.
-    std::vector<int> order((size_t)ST_COUNT * nb);
-    for (int s = 0; s < ST_COUNT; ++s) {
-        int *o = &order[(size_t)s * nb];
-        for (int b = 0; b < nb; ++b) o[b] = b;
-        auto zlen = [&](int b) {
-            const Geo &g = P->geos[b];
-            if (s == ST_FLUX) return g.tzs2 < g.n[2] ? g.tzs2 : g.n[2];
-            if (s == ST_TRACE) return g.tzs1 < g.n[2] + 2 ? g.tzs1 : g.n[2] + 2;
-            return 0;
-        };
-        std::stable_sort(o, o + nb, [&](int a, int b) { return zlen(a) > zlen(b); });
-    }
-    for (int s = 0; s < ST_COUNT; ++s) {
-        unsigned long long acc = 0;
-        for (int i = 0; i < nb; ++i) {
-            pre[(size_t)s * (nb + 1) + i] = (unsigned)acc;
-            acc += (unsigned long long)stage_blocks(P->geos[order[(size_t)s * nb + i]], s);
-        }
-        if (acc >= (1ULL << 31)) {
-            delete P;
-            return HYDRO_EINVAL;
-        }
-        pre[(size_t)s * (nb + 1) + nb] = (unsigned)acc;
-        P->grid[s] = (long long)acc;
-    }
-    // the species stages take the boxes in the given order
-    std::vector<unsigned> spre((size_t)SPS_COUNT * (nb + 1));
-    std::vector<long long> epre(nb + 1);
-    for (int s = 0; s < SPS_COUNT; ++s) {
-        unsigned long long acc = 0;
-        for (int b = 0; b < nb; ++b) {
-            spre[(size_t)s * (nb + 1) + b] = (unsigned)acc;
-            acc += (unsigned long long)species_stage_blocks(P->geos[b], s);
-        }
-        if (acc >= (1ULL << 31)) {
-            delete P;
-            return HYDRO_EINVAL;
-        }
-        spre[(size_t)s * (nb + 1) + nb] = (unsigned)acc;
-        P->sp_grid[s] = (long long)acc;
-    }
-    epre[0] = 0;
-    for (int b = 0; b < nb; ++b)
-        epre[b + 1] = epre[b] + mf_stride(P->geos[b].n[0], P->geos[b].n[1], P->geos[b].n[2]);
-    P->etot = epre[nb];
-    size_t szg = sizeof(Geo) * nb, szw = sizeof(long long) * nb,
-           szo = sizeof(int) * order.size(), szp = sizeof(unsigned) * pre.size(),
-           szs = sizeof(unsigned) * spre.size(), sze = sizeof(long long) * epre.size();
-    size_t offw = (szg + 255) / 256 * 256, offo = offw + (szw + 255) / 256 * 256,
-           offp = offo + (szo + 255) / 256 * 256, offs = offp + (szp + 255) / 256 * 256,
-           offe = offs + (szs + 255) / 256 * 256;
-    if (hipMalloc(&P->dev, offe + sze) != hipSuccess) {
-        delete P;
-        return HYDRO_EHIP;
-    }
-    char *base = (char *)P->dev;
-    if (hipMemcpy(base, P->geos.data(), szg, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(base + offw, wsoff.data(), szw, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(base + offo, order.data(), szo, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(base + offp, pre.data(), szp, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(base + offs, spre.data(), szs, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(base + offe, epre.data(), sze, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(P->dev);
-        delete P;
-        return HYDRO_EHIP;
-    }
-    P->geos_dev = (const Geo *)base;
-    P->wsoff_dev = (const long long *)(base + offw);
-    for (int s = 0; s < ST_COUNT; ++s)
-        P->order_dev[s] = (const int *)(base + offo) + (size_t)s * nb;
-    for (int s = 0; s < ST_COUNT; ++s)
-        P->pre_dev[s] = (const unsigned *)(base + offp) + (size_t)s * (nb + 1);
-    for (int s = 0; s < SPS_COUNT; ++s)
-        P->sp_pre_dev[s] = (const unsigned *)(base + offs) + (size_t)s * (nb + 1);
-    P->epre_dev = (const long long *)(base + offe);
     *plan_out = P;
     return HYDRO_OK;
+}
+
+hydro_status hydro_plan_create_capacity(int capacity, const char *autotune_json, void **plan_out)
+{
+    if (capacity < 1 || capacity > kMaxPlanBoxes || !plan_out) return HYDRO_EINVAL;
+    *plan_out = nullptr;
+    Plan *P = new (std::nothrow) Plan();
+    if (!P) return HYDRO_EINVAL;
+    hydro_status rc = plan_init(P, capacity, autotune_json);
+    if (rc == HYDRO_OK) rc = plan_alloc(P, kPlanStaging);
+    if (rc != HYDRO_OK) {
+        plan_free(P);
+        return rc;
+    }
+    P->nb = 0;
+    *plan_out = P;
+    return HYDRO_OK;
+}
+
+hydro_status hydro_plan_update(void *plan, const hydro_box *boxes, int nb, void *stream)
+{
+    Plan *P = (Plan *)plan;
+    if (!P || P->nstage == 0 || !boxes || nb < 1 || nb > P->cap) return HYDRO_EINVAL;
+    // validate into a copy first, so a rejected update leaves the plan as it was
+    Plan Q;
+    Q.cap = P->cap;
+    Q.rules = P->rules;
+    hydro_status rc = plan_build(&Q, boxes, nb);
+    if (rc != HYDRO_OK) return rc;
+    // the next pinned staging buffer; wait only for the copy that last used it
+    const int k = P->next_stage;
+    if (P->stage_used[k] && hipEventSynchronize(P->stage_ev[k]) != hipSuccess) return HYDRO_EHIP;
+    memcpy(P->stage[k], Q.image.data(), Q.image.size());
+    const hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(P->dev, P->stage[k], Q.image.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipEventRecord(P->stage_ev[k], st) != hipSuccess)
+        return HYDRO_EHIP;
+    P->stage_used[k] = 1;
+    P->next_stage = (k + 1) % P->nstage;
+    // host-side fields: every launch enqueued from here on uses the new lists
+    P->nb = Q.nb;
+    P->boxes.swap(Q.boxes);
+    P->geos.swap(Q.geos);
+    P->ws_bytes = Q.ws_bytes;
+    memcpy(P->grid, Q.grid, sizeof P->grid);
+    memcpy(P->sp_grid, Q.sp_grid, sizeof P->sp_grid);
+    P->etot = Q.etot;
+    return HYDRO_OK;
+}
+
+int hydro_plan_boxes(const void *plan)
+{
+    const Plan *P = (const Plan *)plan;
+    return P ? P->nb : -1;
+}
+
+size_t hydro_plan_workspace_bytes(const void *plan)
+{
+    const Plan *P = (const Plan *)plan;
+    return P ? P->ws_bytes : 0;
 }
 
 void hydro_plan_destroy(void *plan)
 {
     Plan *P = (Plan *)plan;
     if (!P) return;
-    if (P->dev) (void)hipFree(P->dev);
-    delete P;
+    plan_free(P);
 }
 
 static Launch batch_launch(const Plan *P, double *const *Us, double *const *Uns, void *ws,
@@ -1026,7 +1162,7 @@ hydro_status estimate_dt_boxes(int nb, double *const *U_ptrs_dev, const void *pl
                                void *stream)
 {
     const Plan *P = (const Plan *)plan;
-    if (!P || nb != P->nb || !U_ptrs_dev || !dt_dev || !params_valid(prm))
+    if (!P || nb < 1 || nb != P->nb || !U_ptrs_dev || !dt_dev || !params_valid(prm))
         return HYDRO_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     Launch L = batch_launch(P, U_ptrs_dev, nullptr, nullptr, nullptr, 0);
@@ -1053,7 +1189,7 @@ hydro_status advance_boxes(int nb, const double *const *U_ptrs_dev,
                            size_t ws_bytes, int32_t *err_dev, void *stream)
 {
     const Plan *P = (const Plan *)plan;
-    if (!P || nb != P->nb || !U_ptrs_dev || !U_new_ptrs_dev || !dt_dev || !ws_dev ||
+    if (!P || nb < 1 || nb != P->nb || !U_ptrs_dev || !U_new_ptrs_dev || !dt_dev || !ws_dev ||
         !err_dev || !params_valid(prm) || (dt_stride != 0 && dt_stride != 1) ||
         (dt_next_min_dev && !dt_next_dev) || !flatten_ok(prm, P->boxes.data(), P->nb))
         return HYDRO_EINVAL;
@@ -1091,7 +1227,7 @@ hydro_status hydro_fill_ghosts_boxes_species(int nb, double *const *S_ptrs_dev, 
                                              const void *plan, void *stream)
 {
     const Plan *P = (const Plan *)plan;
-    if (!P || nb != P->nb || !S_ptrs_dev || nspec < 1 || nspec > kMaxSpecies)
+    if (!P || nb < 1 || nb != P->nb || !S_ptrs_dev || nspec < 1 || nspec > kMaxSpecies)
         return HYDRO_EINVAL;
     SpArgs A;
     memset(&A, 0, sizeof A);
@@ -1117,7 +1253,7 @@ hydro_status advance_boxes_species(int nb, const double *const *U_ptrs_dev,
                                    int32_t *err_dev, void *stream)
 {
     const Plan *P = (const Plan *)plan;
-    if (!P || nb != P->nb || !S_ptrs_dev || !S_new_ptrs_dev || !sws_dev || nspec < 1 ||
+    if (!P || nb < 1 || nb != P->nb || !S_ptrs_dev || !S_new_ptrs_dev || !sws_dev || nspec < 1 ||
         nspec > kMaxSpecies || ((uintptr_t)sws_dev & 255) ||
         (ws_dev && overlaps(sws_dev, sws_bytes, ws_dev, ws_bytes)))
         return HYDRO_EINVAL;
@@ -1171,7 +1307,7 @@ hydro_status hydro_fill_ghosts_boxes(int nb, double *const *U_ptrs_dev, const vo
                                      void *stream)
 {
     const Plan *P = (const Plan *)plan;
-    if (!P || nb != P->nb || !U_ptrs_dev) return HYDRO_EINVAL;
+    if (!P || nb < 1 || nb != P->nb || !U_ptrs_dev) return HYDRO_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     Launch L = batch_launch(P, U_ptrs_dev, nullptr, nullptr, nullptr, 0);
     L.pre = P->pre_dev[ST_FILL];

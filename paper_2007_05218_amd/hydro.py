@@ -28,7 +28,9 @@ EXPORTS = ("hydro_state_elems", "hydro_workspace_bytes", "hydro_fill_ghosts", "e
            "hydro_level_create", "hydro_level_destroy", "hydro_fill_ghosts_level",
            "hydro_species_workspace_bytes", "hydro_fill_ghosts_species", "advance_box_species",
            "hydro_species_workspace_bytes_boxes", "hydro_fill_ghosts_boxes_species",
-           "advance_boxes_species", "hydro_fill_ghosts_level_species")
+           "advance_boxes_species", "hydro_fill_ghosts_level_species",
+           "hydro_plan_create_capacity", "hydro_plan_update", "hydro_plan_boxes",
+           "hydro_plan_workspace_bytes")
 
 
 class HydroBox(C.Structure):
@@ -73,6 +75,12 @@ def lib():
         L.advance_boxes.argtypes = [C.c_int, vp, vp, vp, pp, vp, C.c_int, vp, vp, vp,
                                     C.c_size_t, vp, vp]
         L.hydro_plan_create.argtypes = [bp, C.c_int, C.c_char_p, C.POINTER(vp)]
+        L.hydro_plan_create_capacity.argtypes = [C.c_int, C.c_char_p, C.POINTER(vp)]
+        L.hydro_plan_update.argtypes = [vp, bp, C.c_int, vp]
+        L.hydro_plan_boxes.argtypes = [vp]
+        L.hydro_plan_boxes.restype = C.c_int
+        L.hydro_plan_workspace_bytes.argtypes = [vp]
+        L.hydro_plan_workspace_bytes.restype = C.c_size_t
         L.hydro_plan_destroy.argtypes = [vp]
         L.hydro_plan_destroy.restype = None
         L.hydro_stage_count.argtypes = []
@@ -105,7 +113,8 @@ def lib():
                   "advance_boxes", "hydro_plan_create", "hydro_fill_ghosts_boxes",
                   "hydro_level_create", "hydro_fill_ghosts_level", "hydro_fill_ghosts_species",
                   "advance_box_species", "hydro_fill_ghosts_boxes_species",
-                  "advance_boxes_species", "hydro_fill_ghosts_level_species"):
+                  "advance_boxes_species", "hydro_fill_ghosts_level_species",
+                  "hydro_plan_create_capacity", "hydro_plan_update"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -296,8 +305,11 @@ class SpeciesBox(Box):
 
 
 class Plan:
-    """A plan for a fixed list of boxes (hydro_plan_create): validated boxes,
-    per-stage work lists on the device.  Owns one small device buffer."""
+    """A plan for a list of boxes: validated boxes, per-stage work lists on the
+    device.  Owns one small device buffer.  ``Plan(boxes)`` is fixed
+    (hydro_plan_create); ``Plan.with_capacity(n)`` starts empty and takes a
+    new list of up to n boxes with ``update`` (hydro_plan_update: an
+    asynchronous copy on the stream, no device allocation)."""
 
     def __init__(self, boxes, autotune_json=None):
         self.boxes = [dict(b) for b in boxes]
@@ -307,7 +319,31 @@ class Plan:
         _check("hydro_plan_create", lib().hydro_plan_create(arr, len(boxes), js, C.byref(h)))
         self.handle = h
         self.nb = len(boxes)
+        self.capacity = self.nb
         self.ws_bytes = workspace_bytes(self.boxes)
+
+    @classmethod
+    def with_capacity(cls, capacity, autotune_json=None):
+        self = cls.__new__(cls)
+        h = C.c_void_p()
+        js = autotune_json.encode() if autotune_json else None
+        _check("hydro_plan_create_capacity",
+               lib().hydro_plan_create_capacity(int(capacity), js, C.byref(h)))
+        self.handle = h
+        self.boxes = []
+        self.nb = 0
+        self.capacity = int(capacity)
+        self.ws_bytes = 0
+        return self
+
+    def update(self, boxes, stream=None):
+        """Replace the list of boxes (stream-ordered with the batched calls)."""
+        arr = (HydroBox * len(boxes))(*[make_box(b) for b in boxes])
+        _check("hydro_plan_update", lib().hydro_plan_update(self.handle, arr, len(boxes),
+                                                            _stream(stream)))
+        self.boxes = [dict(b) for b in boxes]
+        self.nb = len(boxes)
+        self.ws_bytes = int(lib().hydro_plan_workspace_bytes(self.handle))
 
     def close(self):
         if self.handle:

@@ -6,11 +6,16 @@ a number of steps.  The server admits arriving requests while
 the HBM ledger (state ping-pong buffers plus the request's share of the
 batch workspace) stays within the budget and a slot is free, keeps every
 admitted state resident on the device, and advances all active requests
-together: one batched ghost-fill + timestep launch pair and one batched
-advance per iteration (advance_boxes, each box with its own timestep, so a
-request's result does not depend on what it is batched with).  Requests that
-arrive while others run join at the next iteration; finished ones leave
-immediately and their memory returns to the ledger.
+together: one batched ghost-fill (or timestep) launch and one batched advance
+per iteration for each set of method parameters (advance_boxes, each box
+with its own timestep, so a request's result does not depend on what it is
+batched with).  Requests that arrive while others run join at the next
+iteration; finished ones leave immediately and their memory returns to the
+ledger.  Joining and leaving rewrite the work list of a plan made once with
+a capacity (hydro_plan_update) and the batch's pointer arrays by
+asynchronous copies from pinned memory, and a request's initial state is
+uploaded the same way: the loop never waits for the device except to bound
+how far it runs ahead.
 
 The paper's codes keep all simulation data on the GPU and copy to the host
 only for checkpoints (Sec. III), reuse device memory through a caching pool
@@ -50,11 +55,93 @@ class Request:
         self.payload = spec.get("state")
 
 
-class GpuExecutor:
-    """Device side of the server: states in device memory, one batched plan per
-    membership of the active set, every launch on one stream."""
+def _params_key(prm):
+    return (float(prm["gamma"]), float(prm["cfl"]), tuple(float(g) for g in prm["grav"]),
+            int(prm.get("flatten", 0)))
 
-    def __init__(self, device="cuda", keep_results=False, capture_graphs=False):
+
+class _Group:
+    """The active requests that share one set of method parameters: advanced
+    by one batched call per stage with one capacity plan, one workspace that
+    only grows, per-slot timesteps and pointer arrays, all on one stream.
+    Membership changes rewrite the plan's work list and the pointer arrays by
+    asynchronous copies from pinned host memory; nothing synchronises the
+    host with the device."""
+
+    RING = 8  # pinned staging slots for the pointer arrays
+
+    def __init__(self, ex, prm):
+        torch, hydro = ex.torch, ex.hydro
+        self.ex = ex
+        self.prm = prm
+        cap = ex.max_active
+        self.plan = hydro.Plan.with_capacity(cap)
+        self.ws = torch.empty(256, dtype=torch.uint8, device=ex.device)
+        self.dt = torch.zeros(cap, dtype=torch.float64, device=ex.device)
+        self.dt_next = torch.zeros(cap, dtype=torch.float64, device=ex.device)
+        self.ptr = torch.zeros((2, cap), dtype=torch.int64, device=ex.device)
+        self.pa, self.pb = self.ptr[0], self.ptr[1]
+        self.host = [torch.zeros((2, cap), dtype=torch.int64).pin_memory()
+                     for _ in range(self.RING)]
+        self.host_ev = [None] * self.RING
+        self.slot = 0
+        self.members = []
+        self.have_dt = False
+
+    def set_members(self, reqs):
+        torch = self.ex.torch
+        self.members = list(reqs)
+        if not reqs:
+            return
+        n = len(reqs)
+        self.plan.update([r.handle["box"] for r in reqs])
+        if self.plan.ws_bytes > self.ws.numel():
+            # grown geometrically; the caching allocator reuses the old block
+            # in stream order
+            self.ws = torch.empty(max(self.plan.ws_bytes, int(1.25 * self.ws.numel())),
+                                  dtype=torch.uint8, device=self.ex.device)
+        k = self.slot
+        self.slot = (k + 1) % self.RING
+        if self.host_ev[k] is not None:
+            self.host_ev[k].synchronize()  # the copy that last used this slot
+        h = self.host[k]
+        h[0, :n] = torch.tensor([r.handle["U"].data_ptr() for r in reqs], dtype=torch.int64)
+        h[1, :n] = torch.tensor([r.handle["Un"].data_ptr() for r in reqs], dtype=torch.int64)
+        # (stream-ordered: launches queued before this copy still read the old
+        # pointers, later ones the new)
+        self.ptr[:, :n].copy_(h[:, :n], non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        self.host_ev[k] = ev
+        self.pa, self.pb = self.ptr[0], self.ptr[1]
+        self.have_dt = False  # the membership changed: timesteps from estimate_dt_boxes
+
+    def step(self):
+        if not self.members:
+            return
+        h = self.ex.hydro
+        if self.have_dt:  # timesteps of the states the previous iteration produced
+            h.fill_ghosts_boxes(self.plan, self.pa)
+            self.dt, self.dt_next = self.dt_next, self.dt
+        else:
+            h.estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, None)
+        h.advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt, self.ws, self.ex.err,
+                        dt_stride=1, dt_next=self.dt_next)
+        self.have_dt = True
+        for r in self.members:
+            r.handle["U"], r.handle["Un"] = r.handle["Un"], r.handle["U"]
+        self.pa, self.pb = self.pb, self.pa
+
+    def close(self):
+        self.plan.close()
+
+
+class GpuExecutor:
+    """Device side of the server: states in device memory, one group per set
+    of method parameters (each with a capacity plan updated in place as
+    requests join and leave), every launch on the current stream."""
+
+    def __init__(self, device="cuda", keep_results=False, max_active=64):
         import torch
         from . import hydro, inputs
         self.torch = torch
@@ -62,17 +149,16 @@ class GpuExecutor:
         self.inputs = inputs
         self.device = device
         self.keep_results = keep_results
+        self.max_active = int(max_active)
         hydro.lib()
-        self.stream = torch.cuda.current_stream()
-        self.active = []
-        self.plan = None
-        self.retired = []  # plans of earlier batches, freed once the device is idle
-        self.prm = None
+        self.groups = {}
         self.err = torch.zeros(1, dtype=torch.int32, device=device)
 
-    # -- memory ledger
+    # -- memory ledger: state ping-pong buffers plus the box's workspace share
     def bytes_needed(self, req):
-        box = self.inputs.box_desc((req.n,) * 3)
+        # (the sizes depend only on the box's cell counts and ghost depth: a
+        # request without a state gets the families' cubic box)
+        box = req.payload[1] if req.payload is not None else self.inputs.box_desc((req.n,) * 3)
         return 2 * 8 * self.hydro.state_elems(box) + self.hydro.workspace_bytes(box)
 
     # -- membership
@@ -84,10 +170,14 @@ class GpuExecutor:
         else:
             U, box, prm = self.inputs.request_state({"family": req.family, "n": req.n,
                                                      "seed": req.seed})
-        if self.prm is None:
-            self.prm = prm
-        Ud = torch.as_tensor(U).to(self.device, non_blocking=False)
-        req.handle = {"U": Ud, "Un": torch.empty_like(Ud), "box": box}
+        key = _params_key(prm)
+        if key not in self.groups:
+            self.groups[key] = _Group(self, dict(prm))
+        # pinned staging and an asynchronous upload: the host does not wait for
+        # the device work already queued
+        Ud = torch.as_tensor(U, dtype=torch.float64).pin_memory().to(self.device,
+                                                                    non_blocking=True)
+        req.handle = {"U": Ud, "Un": torch.empty_like(Ud), "box": box, "group": key}
 
     def release(self, req):
         if self.keep_results:
@@ -95,41 +185,19 @@ class GpuExecutor:
         req.handle = None
 
     def set_batch(self, reqs):
-        torch = self.torch
-        self.active = list(reqs)
-        if self.plan is not None:
-            # (freeing device memory waits for all queued work: the plan is
-            # kept until the loop has drained the device)
-            self.retired.append(self.plan)
-            self.plan = None
-        if not reqs:
-            return
-        boxes = [r.handle["box"] for r in reqs]
-        self.plan = self.hydro.Plan(boxes)
-        self.ws = torch.empty(max(self.plan.ws_bytes, 256), dtype=torch.uint8, device=self.device)
-        self.dt = torch.zeros(len(reqs), dtype=torch.float64, device=self.device)
-        self.dt_next = torch.zeros(len(reqs), dtype=torch.float64, device=self.device)
-        self.have_dt = False  # the active set changed: timesteps from estimate_dt_boxes
-        self._pointers()
-
-    def _pointers(self):
-        self.pa = self.hydro.pointer_array([r.handle["U"] for r in self.active], self.device)
-        self.pb = self.hydro.pointer_array([r.handle["Un"] for r in self.active], self.device)
+        if len(reqs) > self.max_active:
+            raise ValueError("more active requests than the executor's capacity")
+        by = {k: [] for k in self.groups}
+        for r in reqs:
+            by[r.handle["group"]].append(r)
+        for k, g in self.groups.items():
+            if [id(r) for r in by[k]] != [id(r) for r in g.members]:
+                g.set_members(by[k])
 
     # -- one iteration: every active request advances one step with its own dt
     def step(self):
-        h = self.hydro
-        if self.have_dt:  # timesteps of the states the previous iteration produced
-            h.fill_ghosts_boxes(self.plan, self.pa)
-            self.dt, self.dt_next = self.dt_next, self.dt
-        else:
-            h.estimate_dt_boxes(self.plan, self.pa, self.prm, self.dt, None)
-        h.advance_boxes(self.plan, self.pa, self.pb, self.prm, self.dt, self.ws, self.err,
-                        dt_stride=1, dt_next=self.dt_next)
-        self.have_dt = True
-        for r in self.active:
-            r.handle["U"], r.handle["Un"] = r.handle["Un"], r.handle["U"]
-        self.pa, self.pb = self.pb, self.pa
+        for g in self.groups.values():
+            g.step()
 
     def mark(self):
         ev = self.torch.cuda.Event(enable_timing=True)
@@ -145,11 +213,10 @@ class GpuExecutor:
     def error_bits(self):
         return int(self.err.item())
 
-    def drained(self):
-        """The device has finished all queued work: free retired plans."""
-        for p in self.retired:
-            p.close()
-        self.retired = []
+    def close(self):
+        for g in self.groups.values():
+            g.close()
+        self.groups = {}
 
 
 class Server:
@@ -184,6 +251,9 @@ class Server:
         t0 = self.clock()
         t0_tok = self.ex.mark()
         changed = False
+        cap = getattr(self.ex, "max_active", None)
+        if cap is not None and cap < self.max_active:
+            raise ValueError("the executor holds %d requests, fewer than max_active" % cap)
         while pending or active:
             now = self.clock() - t0
             # admission: FIFO, while a slot and the budget allow
@@ -200,8 +270,6 @@ class Server:
                 # idle until the next arrival (the device drains meanwhile)
                 while inflight:
                     self.ex.wait(inflight.popleft())
-                if hasattr(self.ex, "drained"):
-                    self.ex.drained()
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
                     self.sleep(wait)
@@ -230,8 +298,6 @@ class Server:
                 self.ex.wait(inflight.popleft())
         while inflight:
             self.ex.wait(inflight.popleft())
-        if hasattr(self.ex, "drained"):
-            self.ex.drained()
         for r in done:
             r.t_done = self.ex.elapsed(t0_tok, r.done_token)
         self.requests = sorted(done, key=lambda r: r.id)

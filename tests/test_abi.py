@@ -109,6 +109,14 @@ def test_null_and_overlap_rejected():
     assert L.advance_boxes(1, a, a, None, C.byref(p), a, 1, None, None, ws, nbytes, a,
                            None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_boxes(1, a, None, None) == hydro.HYDRO_EINVAL
+    # workspace overlapping the old or the new state
+    ub = 5 * 16 ** 3 * 8
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), C.c_void_p(1 << 36),
+                         None, C.c_void_p((1 << 30) + ub - 256), nbytes, a,
+                         None) == hydro.HYDRO_EINVAL
+    assert L.advance_box(a, C.c_void_p(1 << 32), C.byref(b), C.byref(p), C.c_void_p(1 << 36),
+                         None, C.c_void_p((1 << 32) - 256), nbytes, a,
+                         None) == hydro.HYDRO_EINVAL
     # flattening reads the fourth ghost layer: a box with three is refused
     d3 = inputs.box_desc((8, 8, 8), ng=3, bc_lo=(1, 1, 1))
     b3 = hydro.make_box(d3)
@@ -216,6 +224,10 @@ def test_species_sizes_and_rejections():
     assert call(S, Sn, 2, sws, nsws - 256) == hydro.HYDRO_ENOWS
     assert call(S, Sn, 2, sws, nsws, Un=C.c_void_p((1 << 30) + 8)) == hydro.HYDRO_EINVAL
     assert call(S, ws, 2, sws, nsws) == hydro.HYDRO_EINVAL                      # S_new over ws
+    assert call(C.c_void_p(1 << 32), Sn, 2, sws, nsws) == hydro.HYDRO_EINVAL    # S over U_new
+    assert call(ws, Sn, 2, sws, nsws) == hydro.HYDRO_EINVAL                     # S over ws
+    assert call(S, Sn, 2, sws, nsws, U=ws) == hydro.HYDRO_EINVAL                # U over ws
+    assert call(S, Sn, 2, sws, nsws, Un=ws) == hydro.HYDRO_EINVAL               # U_new over ws
     assert call(S, Sn, 2, sws, nsws, U=None) == hydro.HYDRO_EINVAL              # before sizes
     assert call(S, Sn, 2, sws, 0, U=None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_species(None, 2, C.byref(b), None) == hydro.HYDRO_EINVAL
@@ -236,3 +248,17 @@ def test_batched_species_sizes_and_rejections():
                                    None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_boxes_species(2, a, 2, None, None) == hydro.HYDRO_EINVAL
     assert L.hydro_fill_ghosts_level_species(2, a, 2, None, None) == hydro.HYDRO_EINVAL
+
+
+def test_capacity_plan_argument_errors():
+    # checked before any device allocation or copy: no GPU needed
+    L = hydro.lib()
+    h = C.c_void_p(123)
+    assert L.hydro_plan_create_capacity(0, None, C.byref(h)) == hydro.HYDRO_EINVAL
+    assert L.hydro_plan_create_capacity((1 << 20) + 1, None, C.byref(h)) == hydro.HYDRO_EINVAL
+    assert L.hydro_plan_create_capacity(4, b'{"16x16x16": [12, 8]}', C.byref(h)) == \
+        hydro.HYDRO_EINVAL
+    arr = (hydro.HydroBox * 1)(hydro.make_box(inputs.box_desc((16, 16, 16))))
+    assert L.hydro_plan_update(None, arr, 1, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_plan_boxes(None) == -1
+    assert L.hydro_plan_workspace_bytes(None) == 0

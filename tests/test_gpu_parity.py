@@ -233,19 +233,48 @@ DEGENERATE = {
 def test_degenerate_and_extreme_boxes_bitwise(gpu, orc, case):
     U, box, prm, *steps = DEGENERATE[case]()
     steps = steps[0] if steps else 5
-    g, gdt, gerr = _gpu_run(gpu, U, box, prm, steps)
-    o, odt, oerr = _oracle_run(orc, U, box, prm, steps)
-    print(case, "err bits gpu %d oracle %d" % (gerr, oerr), flush=True)
     if case == "rarefaction_nonfinite":
         # the last step starts from a state with p < 0 somewhere, whose CFL
         # timestep is unspecified (the square root of a negative pressure):
-        # exact up to there, and both sides flag the non-finite result
-        assert gdt[:-1] == odt[:-1] and (gerr & 1) and (oerr & 1)
+        # both sides take that step with the previous step's timestep, and
+        # must agree on every value (non-finite ones by position) and bit
+        _nonfinite_last_step(gpu, orc, U, box, prm, steps)
         return
+    g, gdt, gerr = _gpu_run(gpu, U, box, prm, steps)
+    o, odt, oerr = _oracle_run(orc, U, box, prm, steps)
+    print(case, "err bits gpu %d oracle %d" % (gerr, oerr), flush=True)
     if case == "rarefaction_bits_8_4":
         assert oerr == 12
     assert gdt == odt and gerr == oerr
     assert np.array_equal(inputs.valid(g, box), inputs.valid(o, box))
+
+
+def _nonfinite_last_step(gpu, orc, U, box, prm, steps):
+    import torch
+    g, gdt, gerr = _gpu_run(gpu, U, box, prm, steps - 1)
+    o, odt, oerr = _oracle_run(orc, U, box, prm, steps - 1)
+    assert gdt == odt and gerr == oerr
+    assert np.array_equal(inputs.valid(g, box), inputs.valid(o, box))
+    dt = odt[-1]
+    Ud = torch.as_tensor(g).cuda()
+    Un = torch.empty_like(Ud)
+    ws = gpu.alloc_workspace(box)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gpu.fill_ghosts(Ud, box)
+    gpu.advance_box(Ud, Un, box, prm, torch.tensor([dt], dtype=torch.float64, device="cuda"),
+                    ws, err)
+    torch.cuda.synchronize()
+    ob, op = orc.box_from(box), orc.params_from(prm)
+    orc.fill_ghosts(o, ob)
+    o5 = o.copy()
+    oerr5 = orc.advance_box(o, o5, ob, op, dt)
+    gerr5 = int(err.item())
+    a, b = inputs.valid(Un.cpu().numpy(), box), inputs.valid(o5, box)
+    print("last step: err bits gpu %d oracle %d, non-finite values %d"
+          % (gerr5, oerr5, int((~np.isfinite(b)).sum())), flush=True)
+    assert gerr5 == oerr5 and (oerr5 & 1)
+    assert np.array_equal(np.isfinite(a), np.isfinite(b))
+    assert np.array_equal(a, b, equal_nan=True)
 
 
 @pytest.mark.parametrize("case", ["kh32", "rt32", "sedov40_flat"])

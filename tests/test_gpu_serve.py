@@ -90,3 +90,51 @@ def test_graph_replay_equals_eager(gpu):
         for a, b, box in zip(got, refs[rep], boxes):
             assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box)), rep
     assert int(lev.err.item()) == 0
+
+
+def test_capacity_plan_updates_are_stream_ordered(gpu):
+    # one plan made with a capacity, refilled for several lists of boxes with
+    # no host synchronisation in between (more updates than it has staging
+    # buffers): every list's step equals the same step with a fixed plan
+    import torch
+    states, boxes, prm = inputs.level(nboxes=12, seed=4)
+    lists = [[0, 1, 2, 3, 4], [2, 5, 6], [7, 8, 9, 10, 11, 0, 3], [4], [1, 9, 5, 11],
+             [6, 7], [10, 2, 8]]
+    cap = gpu.Plan.with_capacity(8)
+    assert gpu.lib().hydro_plan_boxes(cap.handle) == 0
+    U = [torch.as_tensor(u).cuda() for u in states]
+    ws = torch.empty(max(gpu.workspace_bytes(boxes), 256), dtype=torch.uint8, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    # every buffer first, so that the loop below enqueues only
+    outs = [[torch.empty_like(U[b]) for b in sel] for sel in lists]
+    ptrs = [(gpu.pointer_array([U[b] for b in sel]), gpu.pointer_array(Un))
+            for sel, Un in zip(lists, outs)]
+    dts = [torch.zeros(len(sel), dtype=torch.float64, device="cuda") for sel in lists]
+    torch.cuda.synchronize()
+    for sel, (pa, pb), dt in zip(lists, ptrs, dts):
+        cap.update([boxes[b] for b in sel])
+        assert cap.ws_bytes == gpu.workspace_bytes([boxes[b] for b in sel])
+        gpu.estimate_dt_boxes(cap, pa, prm, dt)
+        gpu.advance_boxes(cap, pa, pb, prm, dt, ws, err, dt_stride=1)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    for sel, got in zip(lists, outs):
+        fixed = gpu.Plan([boxes[b] for b in sel])
+        Un = [torch.empty_like(U[b]) for b in sel]
+        pa, pb = gpu.pointer_array([U[b] for b in sel]), gpu.pointer_array(Un)
+        dt = torch.zeros(len(sel), dtype=torch.float64, device="cuda")
+        gpu.estimate_dt_boxes(fixed, pa, prm, dt)
+        gpu.advance_boxes(fixed, pa, pb, prm, dt, ws, err, dt_stride=1)
+        torch.cuda.synchronize()
+        for b, x, y in zip(sel, got, Un):
+            assert np.array_equal(inputs.valid(x.cpu().numpy(), boxes[b]),
+                                  inputs.valid(y.cpu().numpy(), boxes[b])), (sel, b)
+        fixed.close()
+    # refused updates leave the plan as it was
+    with pytest.raises(gpu.HydroError):
+        cap.update(boxes[:9])  # beyond the capacity
+    bad = dict(boxes[0], n=(0, 4, 4))
+    with pytest.raises(gpu.HydroError):
+        cap.update([boxes[1], bad])
+    assert gpu.lib().hydro_plan_boxes(cap.handle) == len(lists[-1])
+    cap.close()
