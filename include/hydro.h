@@ -135,6 +135,25 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
                          const hydro_params *prm, const double *dt_dev, double *dt_next_dev,
                          void *ws_dev, size_t ws_bytes, int32_t *err_dev, void *stream);
 
+/* advance_box for callers that cannot allocate device memory (code under
+ * HIP graph capture that must not call hipMalloc, tight serving loops,
+ * harnesses that forbid allocation): the same step, bitwise the same results
+ * and the same argument rules, without a workspace argument.  The traced
+ * states live instead in a static device array of HYDRO_NOALLOC_WS_BYTES
+ * (128 MiB) that the library holds on every GPU it runs on until the process
+ * ends; the call allocates nothing.  Boxes whose workspace
+ * (hydro_workspace_bytes(box, 1)) exceeds it -- a 78^3 box fits, a 79^3
+ * box does not -- return HYDRO_ENOWS with nothing enqueued.  All calls on one GPU
+ * share that array: calls whose work overlaps in time on one GPU (different
+ * streams, or host threads without ordering between them) race and give
+ * wrong results; calls ordered on one stream are safe.  Its contents on entry
+ * do not matter (the call writes every value it reads).  The first call on a
+ * device looks up the array's address there (HYDRO_EHIP if that fails). */
+#define HYDRO_NOALLOC_WS_BYTES ((size_t)128 << 20)
+hydro_status advance_box_noalloc(const double *U_dev, double *U_new_dev, const hydro_box *box,
+                                 const hydro_params *prm, const double *dt_dev,
+                                 double *dt_next_dev, int32_t *err_dev, void *stream);
+
 /* Passively advected species (the multi-component fluid state of Sec. II's
  * Fabs; the isotopes a reaction network follows, Sec. IV-B): nspec mass
  * fractions X_s (1 <= nspec <= 8) carried by the gas, held as partial

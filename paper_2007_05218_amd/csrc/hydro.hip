@@ -42,6 +42,7 @@
 
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 using namespace hydro;
@@ -964,6 +965,69 @@ hydro_status advance_box(const double *U_dev, double *U_new_dev, const hydro_box
     Launch L = single(g, U_dev, U_new_dev, ws_dev, dt_dev);
     L.dtn = (unsigned long long *)dt_next_dev;
     return enqueue_advance(L, grid, nullptr, nullptr, prm, err_dev, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+
+}  // extern "C"
+
+namespace {
+
+// advance_box_noalloc's workspace: one static device array per GPU, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol); the device
+// address each GPU holds it at is looked up once per device.
+constexpr size_t kNoAllocBytes = HYDRO_NOALLOC_WS_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// device address of `scratch` on the device `stream` runs on
+hydro_status scratch_address(hipStream_t stream, void **out)
+{
+    int cur = -1, dev = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return HYDRO_EHIP;
+    dev = cur;
+    if (stream && hipStreamGetDevice(stream, &dev) != hipSuccess) return HYDRO_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return HYDRO_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur && hipSetDevice(dev) != hipSuccess) return HYDRO_EHIP;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return HYDRO_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hydro_status advance_box_noalloc(const double *U_dev, double *U_new_dev, const hydro_box *box,
+                                 const hydro_params *prm, const double *dt_dev,
+                                 double *dt_next_dev, int32_t *err_dev, void *stream)
+{
+    hydro_status rc = advance_box_args(U_dev, U_new_dev, box, prm, dt_dev, dt_next_dev, err_dev);
+    if (rc != HYDRO_OK) return rc;
+    const Geo g = make_geo(box);
+    const size_t need = box_ws_bytes(g);
+    if (need > kNoAllocBytes) return HYDRO_ENOWS;
+    void *ws = nullptr;
+    const hipStream_t st = (hipStream_t)stream;
+    if ((rc = scratch_address(st, &ws)) != HYDRO_OK) return rc;
+    const size_t ub = 5 * (size_t)g.cs * sizeof(double);
+    if (overlaps(ws, need, U_dev, ub) || overlaps(ws, need, U_new_dev, ub)) return HYDRO_EINVAL;
+    long long grid[ST_COUNT];
+    for (int s = 0; s < ST_COUNT; ++s) grid[s] = stage_blocks(g, s);
+    Launch L = single(g, U_dev, U_new_dev, ws, dt_dev);
+    L.dtn = (unsigned long long *)dt_next_dev;
+    return enqueue_advance(L, grid, nullptr, nullptr, prm, err_dev, st);
 }
 
 size_t hydro_species_workspace_bytes(const hydro_box *box, int nspec)

@@ -28,7 +28,7 @@ EXPORTS = ("hydro_state_elems", "hydro_workspace_bytes", "hydro_fill_ghosts", "e
            "hydro_level_create", "hydro_level_destroy", "hydro_fill_ghosts_level",
            "hydro_species_workspace_bytes", "hydro_fill_ghosts_species", "advance_box_species",
            "hydro_species_workspace_bytes_boxes", "hydro_fill_ghosts_boxes_species",
-           "advance_boxes_species", "hydro_fill_ghosts_level_species",
+           "advance_boxes_species", "hydro_fill_ghosts_level_species", "advance_box_noalloc",
            "hydro_plan_create_capacity", "hydro_plan_update", "hydro_plan_boxes",
            "hydro_plan_workspace_bytes")
 
@@ -71,6 +71,7 @@ def lib():
         L.hydro_fill_ghosts.argtypes = [vp, bp, vp]
         L.estimate_dt.argtypes = [vp, bp, pp, vp, vp]
         L.advance_box.argtypes = [vp, vp, bp, pp, vp, vp, vp, C.c_size_t, vp, vp]
+        L.advance_box_noalloc.argtypes = [vp, vp, bp, pp, vp, vp, vp, vp]
         L.estimate_dt_boxes.argtypes = [C.c_int, vp, vp, pp, vp, vp, vp]
         L.advance_boxes.argtypes = [C.c_int, vp, vp, vp, pp, vp, C.c_int, vp, vp, vp,
                                     C.c_size_t, vp, vp]
@@ -114,7 +115,7 @@ def lib():
                   "hydro_level_create", "hydro_fill_ghosts_level", "hydro_fill_ghosts_species",
                   "advance_box_species", "hydro_fill_ghosts_boxes_species",
                   "advance_boxes_species", "hydro_fill_ghosts_level_species",
-                  "hydro_plan_create_capacity", "hydro_plan_update"):
+                  "advance_box_noalloc", "hydro_plan_create_capacity", "hydro_plan_update"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -188,6 +189,21 @@ def advance_box(U, Unew, box, prm, dt, ws, err, stream=None, dt_next=None):
                                             _ptr(dt_next) if dt_next is not None else None,
                                             _ptr(ws, torch.uint8), ws.numel(),
                                             _ptr(err, torch.int32), _stream(stream)))
+
+
+NOALLOC_WS_BYTES = 128 << 20  # HYDRO_NOALLOC_WS_BYTES
+
+
+def advance_box_noalloc(U, Unew, box, prm, dt, err, stream=None, dt_next=None):
+    """advance_box without a workspace: the library's static per-GPU array of
+    NOALLOC_WS_BYTES holds the traced states (boxes needing more raise
+    HydroError with HYDRO_ENOWS).  Calls overlapping in time on one GPU race."""
+    _check_state(U, box)
+    _check_state(Unew, box)
+    _check("advance_box_noalloc", lib().advance_box_noalloc(
+        _ptr(U), _ptr(Unew), C.byref(make_box(box)), C.byref(make_params(prm)), _ptr(dt),
+        _ptr(dt_next) if dt_next is not None else None, _ptr(err, torch.int32),
+        _stream(stream)))
 
 
 def alloc_workspace(boxes, device="cuda"):
