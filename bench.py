@@ -9,13 +9,19 @@ Rayleigh-Taylor box (FP64, gamma = 1.4, g = -0.1 z, reflecting z walls);
 the library launches on), in cell-updates per second.
 
 Also reported on the same JSON line:
-  roofline      the dominant kernel group's achieved FP64 rate (algorithmic
-                flops per cell-update, counted by the oracle's operation-
-                counting build, x cells / that group's average device time per
-                step, from HIP events recorded by the library around it)
-                against the FP64 VALU issue peak of the chip
+  roofline      the dominant kernel's achieved FP64 rate (algorithmic flops
+                per cell-update, counted by the oracle's operation-counting
+                build, x cells / the kernel's average device time per step,
+                from HIP events the library records around it) against
+                MI355X's published FP64 vector peak (78.6 TFLOP/s), with the
+                single add/multiply issue rate (39.3 T/s) as a labelled
+                second figure; per kernel also its HBM rates (algorithmic
+                bytes and the committed FETCH_SIZE + WRITE_SIZE counters, per
+                launch, over its time) against 8 TB/s and the practical roof
+                of a plain copy kernel timed in the same run
   cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
-                same workload (rank 0, N = 1 only)
+                same workload (rank 0, N = 1 only), with the CPU model and
+                one-thread rates on the Sod 32^3 tube and the KH box at 64^3
   also          secondary workloads: the 256^3 Kelvin-Helmholtz box, also
                 with two passively advected species; the
                 paper's Sedov blast at its per-node size (256^3 as 64 boxes of
@@ -37,9 +43,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 VALU issue peak without FMA: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz
-# (each add or multiply is one instruction; the 78.6 TFLOP/s vector figure
-# counts an FMA as two flops)
+# MI355X's published dense FP64 vector peak (an FMA counted as two flops)
+PEAK_FP64 = 78.6e12
+# the same units' issue rate of single adds or multiplies (the arithmetic
+# contract forbids contracting them into FMAs): 256 CUs x 64 FP64 lanes per
+# clock x 2.4 GHz -- reported beside the published peak, labelled
 PEAK_FP64_NOFMA = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12
 # oracle stages computed by each kernel group of the library's advance
@@ -47,6 +55,11 @@ KERNEL_STAGES = {"trace": ["prim", "trace"],
                  "flux_update": ["flux1", "corner_flux2", "final_flux3", "update"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rt512_traffic.json")
 KERNEL_SYMBOL = {"trace": "k_trace_fused<false>", "flux_update": "k_flux_fused<false>"}
+# each kernel's algorithmic HBM bytes per cell-update (its inputs read once,
+# its outputs written once): the trace kernel reads the state (40 B) and
+# writes the 30 traced face states (240 B) of a cell; the flux kernel reads
+# those and the state and writes the new state (320 B)
+ALG_BYTES = {"trace": 280.0, "flux_update": 320.0}
 
 
 # the sources the profiled step kernels are built from
@@ -90,9 +103,11 @@ def parse():
     ap.add_argument("--workloads", default="rt512,kh256,species,sedov,level,serve",
                     help="comma list of rt512, kh256, sedov, level, serve, copy (a plain 2 GiB "
                          "device copy, the reference for HBM traffic counters)")
-    ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--serve-warmup", type=int, default=20)
-    ap.add_argument("--level-steps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-states", type=int, default=96,
+                    help="distinct initial states the serving stream's requests cycle through")
+    ap.add_argument("--level-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -378,51 +393,77 @@ def time_sedov(hydro, torch, inputs, steps, warmup, n=256, bs=64):
                              "optimal conditions (other hardware, precision not stated)"}
 
 
-def time_serving(inputs, nreq, warm, seed=3):
+def time_serving(torch, inputs, nreq, warm, nstates, seed=3):
     """Continuous-batching server: saturated capacity (all requests at t=0),
-    the same with one request at a time, then a Poisson stream at 80% load;
-    every request arrives with its initial state."""
+    the same with one request at a time, then a Poisson stream at 80% load of
+    `warm` warm-up requests followed by `nreq` measured ones.  Every request
+    arrives with its initial state (the client's payload): `nstates` distinct
+    runs of the serving stream (family, side and seed), built and pinned in
+    host memory before the timed runs, which the stream's requests cycle
+    through, each with its own arrival time and step count.  The server's
+    work starts at admission, with the upload of that state."""
     from paper_2007_05218_amd.serve import GpuExecutor, Server
     import numpy as np
-    # Each request brings its initial state (the client's payload), built
-    # here before the timed runs; the server's work starts at admission,
-    # with the upload of that state to the device.
     from concurrent.futures import ThreadPoolExecutor
-    pool = ThreadPoolExecutor(8)
-    probe = inputs.request_stream(24, rate=0.0, seed=seed + 100)
-    states = list(pool.map(inputs.request_state, probe))
-    for s in probe:
-        s["arrival"] = 0.0
+    base = inputs.request_stream(nstates, rate=1.0, seed=seed + 7)
+    with ThreadPoolExecutor(8) as pool:
+        built = list(pool.map(inputs.request_state, base))
+    payloads = [(torch.from_numpy(U).pin_memory(), box, prm) for U, box, prm in built]
+    del built
+
+    def attach(specs):
+        for i, s in enumerate(specs):
+            k = i % nstates
+            s.update(n=base[k]["n"], family=base[k]["family"], seed=base[k]["seed"],
+                     state=payloads[k])
+        return specs
+
     cap = {}
     for name, slots in (("batched", 64), ("one_at_a_time", 1)):
-        for s, st in zip(probe, states):
-            s["state"] = st
-        srv = Server(GpuExecutor(), budget_bytes=200e9, max_active=slots)
+        probe = attach(inputs.request_stream(24, rate=0.0, seed=seed + 100))
+        srv = Server(GpuExecutor(max_active=64), budget_bytes=200e9, max_active=slots)
         srv.run(probe)
         cap[name] = srv.metrics()["cu_per_s"]
-    del states, probe
-    sample = inputs.request_stream(20000, rate=1.0, seed=seed + 1)
+        srv.ex.close()
+    sample = attach(inputs.request_stream(20000, rate=1.0, seed=seed + 1))
     ework = float(np.mean([r["n"] ** 3 * r["steps"] for r in sample]))
     lam = 0.8 * cap["batched"] / ework
-    specs = inputs.request_stream(nreq, rate=lam, seed=seed)
-    for s, st in zip(specs, pool.map(inputs.request_state, specs)):
-        s["state"] = st
-    pool.shutdown()
-    srv = Server(GpuExecutor(), budget_bytes=200e9, max_active=64)
+    specs = attach(inputs.request_stream(nreq + warm, rate=lam, seed=seed))
+    ex = GpuExecutor(max_active=64)
+    srv = Server(ex, budget_bytes=200e9, max_active=64)
+    t0 = time.perf_counter()
     srv.run(specs)
+    wall = time.perf_counter() - t0
+    ex.close()
     m = srv.metrics(skip=warm)
     m.update({"workload": "serve: Poisson arrivals at 80%% of saturated capacity, cubic n "
                           "log-uniform in [32,192], steps uniform in [10,200], families "
-                          "sod/kh/smooth, 200 GB HBM budget, seed %d" % seed,
+                          "sod/kh/smooth, 200 GB HBM budget, seed %d; %d warm-up + %d "
+                          "measured requests cycling through %d distinct initial states"
+                          % (seed, warm, nreq, nstates),
               "rate_per_s": lam, "mean_work_cu": ework, "warmup_requests": warm,
+              "loop_wall_s": wall,
               "capacity_batched_cu_per_s": cap["batched"],
               "capacity_one_at_a_time_cu_per_s": cap["one_at_a_time"]})
     return m
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(inputs, U, box, prm, seconds):
     """The oracle on z-slabs of the workload's first step until ~`seconds`
-    of host time have been spent."""
+    of host time have been spent, on all the threads OpenMP gives it; then on
+    one thread the Sod 32^3 tube for 20 steps and one step of the
+    Kelvin-Helmholtz box at 64^3."""
     from oracle import build, oracle as orc
     build.build(force=False)
     ob, op = orc.box_from(box), orc.params_from(prm)
@@ -435,6 +476,7 @@ def cpu_baseline(inputs, U, box, prm, seconds):
     Unew = U.copy()
     slab = 4
     cells = 0
+    threads = orc.num_threads()
     t0 = time.perf_counter()
     z = 0
     while time.perf_counter() - t0 < seconds and z < n[2]:
@@ -443,11 +485,25 @@ def cpu_baseline(inputs, U, box, prm, seconds):
         cells += n[0] * n[1] * (hi - z)
         z = hi
     el = time.perf_counter() - t0
-    return ({"value": cells / el, "unit": "cell-updates/s", "cores": orc.num_threads(),
+    del Unew
+    one = {}
+    orc.set_num_threads(1)
+    try:
+        for name, (Ui, bi, pi), steps in (("sod32_20_steps", inputs.sod(32), 20),
+                                          ("kh64_1_step", inputs.kh(64, seed=1), 1)):
+            obi, opi = orc.box_from(bi), orc.params_from(pi)
+            t1 = time.perf_counter()
+            orc.run(Ui, obi, opi, steps)
+            one[name + "_cu_per_s"] = bi["n"][0] * bi["n"][1] * bi["n"][2] * steps / (
+                time.perf_counter() - t1)
+    finally:
+        orc.set_num_threads(threads)
+    return ({"value": cells / el, "unit": "cell-updates/s", "cores": threads,
              "kind": "oracle",
              "sample": "first step of the %dx%dx%d workload on %d z-slabs of %d cells "
                        "(%d cell-updates, %.1f s)" % (n[0], n[1], n[2], z // slab, slab,
-                                                      cells, el)}, ops)
+                                                      cells, el),
+             "cpu_model": cpu_model(), "one_thread": one}, ops)
 
 
 def main():
@@ -465,17 +521,24 @@ def main():
     work = [w.strip() for w in args.workloads.split(",") if w.strip()]
     rank = int(os.environ.get("RANK", "0"))
 
-    if "copy" in work:
-        a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.neg(a, out=b)  # an elementwise kernel: 2 GiB read, 2 GiB written
-        torch.cuda.synchronize()
-        del a, b
-        torch.cuda.empty_cache()
-        log("copy: 2 GiB read + 2 GiB written")
+    # the practical HBM roof: a plain elementwise kernel over 2 GiB (2 GiB
+    # read and 2 GiB written per launch), timed with events
+    a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 1 if "copy" in work else 10  # one launch only under the counters
+    e0.record()
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log("copy: 2 GiB read + 2 GiB written per launch, %.0f GB/s" % copy_gbps)
     log("building RT 512^3 input")
     U, box, prm = inputs.rt(512, seed=4)
     ncell = box["n"][0] * box["n"][1] * box["n"][2]
@@ -501,18 +564,40 @@ def main():
     dom = max(adv, key=adv.get)
     roof = None
     if ops:
-        ach = flops(ops[dom]) * ncell / (stage_ms[dom] * 1e-3)
-        traffic = measured_traffic(dom)
-        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_NOFMA / 1e12,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_NOFMA, "traffic": traffic,
+        step_s = ms / args.steps * 1e-3
+
+        def kernel_entry(k):
+            kms = stage_ms[k]
+            ach = flops(ops[k]) * ncell / (kms * 1e-3)
+            traffic = measured_traffic(k)
+            alg = ALG_BYTES[k] * ncell / (kms * 1e-3)
+            return ach, traffic, {
+                "ms": kms, "achieved_TFLOPs": ach / 1e12, "frac": ach / PEAK_FP64,
+                "frac_of_issue_peak_no_fma": ach / PEAK_FP64_NOFMA,
+                "flops_per_cell_update": flops(ops[k]),
+                "algorithmic_bytes_per_cell_update": ALG_BYTES[k],
+                "algorithmic_GBps": alg / 1e9, "algorithmic_frac_of_8TBps": alg / HBM_PEAK,
+                "counter_bytes_per_launch": traffic,
+                "counter_GBps": traffic / (kms * 1e-3) / 1e9 if traffic else None,
+                "counter_frac_of_8TBps": traffic / (kms * 1e-3) / HBM_PEAK if traffic else None}
+
+        ach, traffic, dom_entry = kernel_entry(dom)
+        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64, "traffic": traffic,
                 "kernel": KERNEL_SYMBOL[dom], "kernel_ms": stage_ms[dom],
                 "flops_per_cell_update": flops(ops[dom]),
-                "step_flops_per_cell_update": flops(ops["step"]),
-                "step_frac": flops(ops["step"]) * ncell / (ms / args.steps * 1e-3) / PEAK_FP64_NOFMA,
-                "other_kernels": {KERNEL_SYMBOL[k]: {"ms": stage_ms[k],
-                                                     "frac": flops(ops[k]) * ncell / (stage_ms[k] * 1e-3) / PEAK_FP64_NOFMA}
-                                  for k in adv if k != dom},
-                "hbm_frac_80B_per_cu": 80.0 * value / HBM_PEAK}
+                "issue_peak_no_fma_TFLOPs": PEAK_FP64_NOFMA / 1e12,
+                "frac_of_issue_peak_no_fma": ach / PEAK_FP64_NOFMA,
+                "kernels": {KERNEL_SYMBOL[k]: (dom_entry if k == dom else kernel_entry(k)[2])
+                            for k in adv},
+                "practical_hbm_copy_GBps": copy_gbps,
+                "step": {"flops_per_cell_update": flops(ops["step"]),
+                         "achieved_TFLOPs": flops(ops["step"]) * ncell / step_s / 1e12,
+                         "frac": flops(ops["step"]) * ncell / step_s / PEAK_FP64,
+                         "frac_of_issue_peak_no_fma":
+                             flops(ops["step"]) * ncell / step_s / PEAK_FP64_NOFMA,
+                         "algorithmic_GBps_80B_per_cu": 80.0 * value / 1e9,
+                         "hbm_frac_80B_per_cu": 80.0 * value / HBM_PEAK}}
 
     also = {}
     if "kh256" in work:
@@ -535,8 +620,9 @@ def main():
         log("timing the 512-box level, batched vs per-box")
         also["level512"] = time_level(hydro, torch, inputs, args.level_steps, 1)
     if "serve" in work:
-        log("serving %d requests" % args.serve_requests)
-        also["serve"] = time_serving(inputs, args.serve_requests, args.serve_warmup)
+        log("serving %d + %d requests" % (args.serve_warmup, args.serve_requests))
+        also["serve"] = time_serving(torch, inputs, args.serve_requests, args.serve_warmup,
+                                     args.serve_states)
         log("serve:", json.dumps(also["serve"]))
 
     out = {"metric": "FP64 hydro cell-updates/s (whole step: ghost fill + CFL dt + CTU-PPM-HLLC advance)",
