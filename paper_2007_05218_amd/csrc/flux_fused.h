@@ -234,20 +234,21 @@ __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long n
 // lane delivers their values with no LDS traffic and no barrier.  (A lane at
 // a row end receives another row's value or its own; nothing it computes
 // from it is used.)
+// (bound_ctrl: the lane at the wavefront's end, which has no source lane,
+// reads zero instead of keeping an old value, so each 32-bit half is one
+// DPP move with no copy of the old value first)
 __device__ __forceinline__ double dpp_prev(double v)  // lane t-1's v
 {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x138, 0xF, 0xF,
-                                               false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 __device__ __forceinline__ double dpp_next(double v)  // lane t+1's v
 {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0x130, 0xF, 0xF,
-                                               false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 // the low x-neighbour's state; its 1/rho is the neighbour's (formed there,
