@@ -161,8 +161,10 @@ hydro_status advance_box_noalloc(const double *U_dev, double *U_new_dev, const h
  * layout (component s at offset s * s0 s1 s2 doubles).
  *
  * Species workspace, in bytes, that advance_box_species needs for this box
- * and species count (the mass fluxes of the gas step and the species
- * pass's face values); 0 for invalid arguments. */
+ * and species count: the mass fluxes of every Riemann solve of the gas step
+ * (twelve face fields), which the species pass reads; the species' own face
+ * values never leave the chip, so the size does not grow with nspec.  0 for
+ * invalid arguments. */
 size_t hydro_species_workspace_bytes(const hydro_box *box, int nspec);
 
 /* Ghost fill of the species array S_dev by the rules of hydro_fill_ghosts,

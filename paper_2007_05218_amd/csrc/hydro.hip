@@ -424,6 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
 #include "flux_fused.h"
 #include "trace_fused.h"
 #include "species.h"
+#include "species_fused.h"
 
 // ---------------------------------------------------------------- host side
 
@@ -662,17 +663,14 @@ bool parse_tiles(const char *js, std::vector<TileRule> &out)
 // ---------------------------------------------------------------- plans
 
 // species stages of a batch (blocks per box: ghost cells of the state
-// layout, cells / faces of the index box, valid cells)
-enum { SPS_FILL, SPS_TRACE, SPS_CORNER, SPS_FINAL, SPS_UPDATE, SPS_COUNT };
+// layout; tiles of the fused pass, whose launch has one block per tile and
+// species)
+enum { SPS_FILL, SPS_FUSED, SPS_COUNT };
 
 __host__ inline long long species_stage_blocks(const Geo &g, int st)
 {
-    const long long nE = (long long)(g.n[0] + 2) * (g.n[1] + 2) * (g.n[2] + 2);
     if (st == SPS_FILL) return (g.cs + kBlock - 1) / kBlock;
-    if (st == SPS_TRACE) return sp_part_blocks(nE, kSpTraceParts);
-    if (st == SPS_CORNER) return sp_part_blocks(nE, kSpCornerParts);
-    if (st == SPS_FINAL) return sp_part_blocks(nE, kSpFinalParts);
-    return ((long long)g.n[0] * g.n[1] * g.n[2] + kBlock - 1) / kBlock;
+    return sp_fused_tiles(g);
 }
 
 // A plan: the per-stage work lists of a list of boxes, in one device
@@ -854,21 +852,15 @@ void plan_free(Plan *P)
     delete P;
 }
 
-// the species pass (trace, corner, final, update) of one box (B.nb == 0)
-// or a batch (B with the plan's species prefixes)
+// the species pass of one box (B.nb == 0) or a batch (B with the plan's
+// tile prefix sums): one fused launch, a block per tile and species
 void enqueue_species(const SpArgs &A, SpBatch B, const long long *grid,
                      const unsigned *const *pre, int32_t *err_dev, hipStream_t st)
 {
-    auto set = [&](int s) {
-        if (B.nb) B.pre = pre[s];
-        return dim3((unsigned)grid[s]);
-    };
+    if (B.nb) B.pre = pre[SPS_FUSED];
     prof(PG_SPECIES, 0, st);
-    hipLaunchKernelGGL(k_sp_trace, set(SPS_TRACE), dim3(kBlock), 0, st, A, B);
-    hipLaunchKernelGGL(k_sp_corner, set(SPS_CORNER), dim3(kBlock), 0, st, A, B);
-    hipLaunchKernelGGL(k_sp_final, set(SPS_FINAL), dim3(kBlock), 0, st, A, B);
-    hipLaunchKernelGGL(k_sp_update, set(SPS_UPDATE), dim3(kBlock), 0, st, A, B,
-                       (int *)err_dev);
+    hipLaunchKernelGGL(k_sp_fused, dim3((unsigned)(grid[SPS_FUSED] * A.ns)), dim3(256), 0, st,
+                       A, B, (int *)err_dev);
     prof(PG_SPECIES, 1, st);
 }
 
@@ -1034,7 +1026,7 @@ size_t hydro_species_workspace_bytes(const hydro_box *box, int nspec)
 {
     if (!box_valid(box) || nspec < 1 || nspec > kMaxSpecies) return 0;
     const Geo g = make_geo(box);
-    return (size_t)(12 + 15 * nspec) * (size_t)mf_stride(g.n[0], g.n[1], g.n[2]) * sizeof(double);
+    return (size_t)12 * (size_t)mf_stride(g.n[0], g.n[1], g.n[2]) * sizeof(double);
 }
 
 hydro_status hydro_fill_ghosts_species(double *S_dev, int nspec, const hydro_box *box,
@@ -1100,9 +1092,6 @@ hydro_status advance_box_species(const double *U_dev, double *U_new_dev, const d
     A.ws = (const char *)ws_dev;
     A.E = mf_stride(g.n[0], g.n[1], g.n[2]);
     A.mf = mf;
-    A.Xt = mf + 12 * A.E;
-    A.G2 = A.Xt + 6 * nspec * A.E;
-    A.G3 = A.G2 + 6 * nspec * A.E;
     A.dt = dt_dev;
     A.ns = nspec;
     A.flat = prm->flatten;
@@ -1321,7 +1310,7 @@ hydro_status advance_boxes_species(int nb, const double *const *U_ptrs_dev,
         nspec > kMaxSpecies || ((uintptr_t)sws_dev & 255) ||
         (ws_dev && overlaps(sws_dev, sws_bytes, ws_dev, ws_bytes)))
         return HYDRO_EINVAL;
-    if (sws_bytes < (size_t)(12 + 15 * nspec) * (size_t)P->etot * sizeof(double))
+    if (sws_bytes < (size_t)12 * (size_t)P->etot * sizeof(double))
         return HYDRO_ENOWS;
     if (!U_ptrs_dev || !U_new_ptrs_dev || !dt_dev || !ws_dev || !err_dev ||
         !params_valid(prm) || (dt_stride != 0 && dt_stride != 1) ||
@@ -1343,7 +1332,7 @@ hydro_status advance_boxes_species(int nb, const double *const *U_ptrs_dev,
     L.dtn = (unsigned long long *)dt_next_dev;
     L.dtn_min = (unsigned long long *)dt_next_min_dev;
     hydro_status rc = enqueue_advance(L, P->grid, P->pre_dev, P->order_dev, prm, err_dev, st,
-                                      (double *)sws_dev, P->epre_dev, 12 + 15 * nspec);
+                                      (double *)sws_dev, P->epre_dev, 12);
     if (rc != HYDRO_OK) return rc;
     SpArgs A;
     memset(&A, 0, sizeof A);

@@ -198,11 +198,11 @@ def test_species_sizes_and_rejections():
     d = inputs.box_desc((8, 8, 8), bc_lo=(1, 1, 1))
     assert hydro.species_workspace_bytes(d, 0) == 0
     assert hydro.species_workspace_bytes(d, 9) == 0
-    # twelve mass-flux fields and 15 per species (traced values, round-2 and
-    # round-3 species fluxes) over the 10^3 index box, each padded to 256 B
+    # the twelve mass-flux fields of the gas step over the 10^3 index box,
+    # each padded to 256 B, whatever the species count
     field = -(-10 ** 3 // 32) * 32 * 8
-    assert hydro.species_workspace_bytes(d, 1) == 27 * field
-    assert hydro.species_workspace_bytes(d, 3) == 57 * field
+    assert hydro.species_workspace_bytes(d, 1) == 12 * field
+    assert hydro.species_workspace_bytes(d, 3) == 12 * field
     L = hydro.lib()
     b = hydro.make_box(d)
     p = hydro.make_params(inputs.params_desc())
