@@ -336,10 +336,15 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
     const long long mfE = EX ? mf_stride(n0, n1, n2) : 0;
     const long long mfP = (long long)(n0 + 2) * (n1 + 2);
     // (a uniform plane base plus the lane's 32-bit byte offset, as for the
-    // workspace: (n0+2)(n1+2) doubles fit 32-bit offsets for every valid box)
+    // workspace: (n0+2)(n1+2) doubles fit 32-bit offsets for every valid box.
+    // The base is formed at each store and kept opaque: otherwise the
+    // compiler hoists the twelve per-lane 64-bit field addresses out of the
+    // z-loop, and they spill)
     const unsigned mfo = (unsigned)((y + 1) * (n0 + 2) + (x + 1)) * 8u;
     auto mf_put = [&](int f, int z, double v) {
-        stb64(mflux + f * mfE + (long long)(z + 1) * mfP, mfo, v);
+        const char *fb = (const char *)(mflux + f * mfE + (long long)(z + 1) * mfP);
+        asm volatile("" : "+s"(fb));
+        stb64((double *)fb, mfo, v);
     };
     unsigned exm = 0;
     if (EX) {
