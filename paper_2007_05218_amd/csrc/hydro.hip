@@ -22,9 +22,11 @@
 //                  source + error bits, and the new state's CFL timestep
 //                  (flux_fused.h); with species, also the mass flux of every
 //                  Riemann solve
-//   k_sp_*         the species pass: trace, corner, final, update of the
-//                  partial densities of passively advected species, carried
-//                  by those mass fluxes (species.h)
+//   k_sp_fused     the species pass: the three rounds of the step for the
+//                  mass fractions of passively advected species, carried by
+//                  those mass fluxes, and the update of their partial
+//                  densities, in one z-march (species_fused.h); k_sp_fill
+//                  fills the species' ghosts (species.h)
 //
 // Batching: a plan lists, for every stage, a work list of the boxes and the
 // prefix sum of their block counts; a block finds its box by binary search,
@@ -217,8 +219,8 @@ struct Launch {
 };
 
 // Faces and cells of the index box [-1, n0] x [-1, n1] x [-1, n2] (faces
-// named by the cell above them): the layout of the mass-flux export and of
-// the species pass's arrays.  Each field is padded to 256 bytes.
+// named by the cell above them): the layout of the mass-flux export, each
+// field padded to 256 bytes.
 __host__ __device__ inline long long mf_stride(int n0, int n1, int n2)
 {
     return ((long long)(n0 + 2) * (n1 + 2) * (n2 + 2) + 31) / 32 * 32;
