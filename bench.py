@@ -75,9 +75,9 @@ def source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter profile,
-    if it was taken on the current kernel sources; else None."""
+def measured_counters(kernel):
+    """Per-launch counters of `kernel` from the committed counter profile, if
+    it was taken on the current kernel sources; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -85,10 +85,35 @@ def measured_traffic(kernel):
         return None
     if t.get("source_hash") != source_hash():
         return None
-    k = t.get("kernels", {}).get(KERNEL_SYMBOL.get(kernel, kernel))
+    return t.get("kernels", {}).get(KERNEL_SYMBOL.get(kernel, kernel))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, scaled),
+    from the committed counter profile; None if it is stale."""
+    k = measured_counters(kernel)
     if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
         return None
     return k["fetch_bytes"] + k["write_bytes"]
+
+
+# FP64 VALU instructions a wave issues: add, multiply, FMA, transcendental
+FP64_INSTS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+              "SQ_INSTS_VALU_TRANS_F64")
+# lane-instruction issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes per clock
+LANE_ISSUE_PER_S = 256 * 64 * 2.4e9
+
+
+def executed_valu(kernel, ncell):
+    """From the committed counters (None if stale): FP64 VALU and all VALU
+    lane-instructions per cell-update of one launch over ncell cells, and the
+    FP64 flops the hardware executed per cell-update (an FMA counted twice)."""
+    k = measured_counters(kernel)
+    if not k or any(c not in k for c in FP64_INSTS + ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP64")):
+        return None
+    return {"fp64_valu_instr_per_cu": 64 * sum(k[c] for c in FP64_INSTS) / ncell,
+            "valu_instr_per_cu": 64 * k["SQ_INSTS_VALU"] / ncell,
+            "executed_fp64_flops_per_cu": 64 * k["SQ_INSTS_VALU_FLOPS_FP64"] / ncell}
 
 
 def log(*a):
@@ -576,6 +601,19 @@ def main():
     if ops:
         step_s = ms / args.steps * 1e-3
 
+        def valu_entry(k, kms):
+            # executed instructions from the committed counters: the FP64
+            # flops the hardware ran per second against the 78.6 T peak, and
+            # the lane-instruction issue rate against the chip's
+            ex = executed_valu(k, ncell)
+            if not ex:
+                return None
+            return dict(ex, **{
+                "executed_fp64_TFLOPs": ex["executed_fp64_flops_per_cu"] * ncell / (kms * 1e-3) / 1e12,
+                "executed_fp64_frac": ex["executed_fp64_flops_per_cu"] * ncell / (kms * 1e-3)
+                / PEAK_FP64,
+                "valu_issue_frac": ex["valu_instr_per_cu"] * ncell / (kms * 1e-3) / LANE_ISSUE_PER_S})
+
         def kernel_entry(k):
             kms = stage_ms[k]
             ach = flops(ops[k]) * ncell / (kms * 1e-3)
@@ -589,7 +627,8 @@ def main():
                 "algorithmic_GBps": alg / 1e9, "algorithmic_frac_of_8TBps": alg / HBM_PEAK,
                 "counter_bytes_per_launch": traffic,
                 "counter_GBps": traffic / (kms * 1e-3) / 1e9 if traffic else None,
-                "counter_frac_of_8TBps": traffic / (kms * 1e-3) / HBM_PEAK if traffic else None}
+                "counter_frac_of_8TBps": traffic / (kms * 1e-3) / HBM_PEAK if traffic else None,
+                "counter_valu": valu_entry(k, kms)}
 
         ach, traffic, dom_entry = kernel_entry(dom)
         roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,
@@ -609,6 +648,19 @@ def main():
                              flops(ops["step"]) * ncell / step_s / PEAK_FP64_NOFMA,
                          "algorithmic_GBps_80B_per_cu": 80.0 * value / 1e9,
                          "hbm_frac_80B_per_cu": 80.0 * value / HBM_PEAK}}
+        # the step against its VALU roof: the FP64 VALU instructions the
+        # advance kernels issue per cell-update (counters), at one lane-
+        # instruction per lane and clock, bounds cell-updates/s
+        exs = [executed_valu(k, ncell) for k in adv]
+        if all(exs):
+            fp64_i = sum(e["fp64_valu_instr_per_cu"] for e in exs)
+            all_i = sum(e["valu_instr_per_cu"] for e in exs)
+            roof["step"].update({
+                "fp64_valu_instr_per_cu": fp64_i, "valu_instr_per_cu": all_i,
+                "fp64_valu_roof_cu_per_s": LANE_ISSUE_PER_S / fp64_i,
+                "frac_of_fp64_valu_roof": value / (LANE_ISSUE_PER_S / fp64_i),
+                "valu_roof_cu_per_s": LANE_ISSUE_PER_S / all_i,
+                "frac_of_valu_roof": value / (LANE_ISSUE_PER_S / all_i)})
 
     also = {}
     if "kh256" in work:
