@@ -2,8 +2,8 @@
 // final states and the conservative update of one species' partial density
 // rho X, for one box tile, marching along z.
 //
-// The arithmetic of every value is that of the staged pass it replaces (the
-// oracle's species stage): X = rho X / rho; each cell's limited parabola of
+// Every value is formed with the species step's own arithmetic, operation
+// for operation: X = rho X / rho; each cell's limited parabola of
 // X along each axis (flattened like the gas) averaged toward each face over
 // the contact wave when it moves toward the face, else over the outermost
 // wave; round-1 species flux = mass flux x X of the side the mass leaves
@@ -11,8 +11,7 @@
 // corrected density (dt/3 of one transverse round-1 difference), the traced
 // X where that density is not positive; round-2 species fluxes; final X
 // (dt/2 of both transverse round-2 differences); round-3 species fluxes;
-// update.  Only the data movement differs: nothing but the partial
-// densities goes back to HBM.
+// update.  Nothing but the new partial densities goes back to HBM.
 //
 // Tile: a 256-thread block covers 16 x 16 columns, the inner 14 x 14 the
 // output columns (the one-column ring supplies the transverse neighbours a
@@ -26,10 +25,9 @@
 // DPP lane shifts inside the wavefront, y-neighbour values through LDS (one
 // barrier per exchange; the next plane's X enters the LDS plane with the
 // last exchange, so an iteration has three), z-neighbour values are carried
-// in registers.  The
-// gas's mass fluxes (all twelve families, exported by the flux kernel), its
-// traced densities (the trace kernel's workspace) and flattening
-// coefficients are read at the lane's own column only.
+// in registers.  The gas's mass fluxes (all twelve families, exported by the
+// flux kernel), its traced densities (the trace kernel's workspace) and
+// flattening coefficients are read at the lane's own column only.
 #pragma once
 
 namespace {
