@@ -1,8 +1,11 @@
 """Tile-shape autotuner for batched levels of boxes.
 
 The two fused kernels of the step (the trace kernel and the flux kernel)
-each process a box in tiles of 256 columns (tbx x 256/tbx, tbx in
-{8, 16, 32}) marching over z-segments of tzs planes.
+each process a box in tiles of columns marching over z-segments of tzs
+planes: the trace kernel tbx x 256/tbx columns (tbx in {8, 16, 32}), the
+flux kernel rows of tbx lanes, 64/tbx whole rows per wavefront (tbx in
+{8, 16, 18, 32}; 18 leaves ten lanes of each wavefront idle but fits boxes
+16 or 32 cells wide, whose 16-lane rows would compute 14 columns each).
 The best tile depends on the box shape: narrow boxes waste halo columns in
 wide tiles, short boxes want short z-segments to expose enough blocks, tall
 ones long segments to amortise the two warm-up planes.  The paper finds the
@@ -19,7 +22,8 @@ import json
 
 from . import hydro, inputs
 
-TBX = (8, 16, 32)
+TBX = (8, 16, 32)        # widths both kernels take
+TBX_FLUX_ONLY = (18,)     # widths only the flux kernel takes
 TZS = (8, 16, 32, 64, 128)
 STAGES = ("trace", "flux_update")
 
@@ -35,8 +39,18 @@ def table_json(table):
 
 
 def candidates(n):
+    """Table entries to time for shape n: (tbx, tzs) for both kernels, and
+    (0, 0, tbx, tzs) for the flux-only widths (the trace kernel built-in)."""
     zs = sorted({z for z in TZS if z < n[2]} | {n[2]})
-    return [(b, z) for b in TBX for z in zs]
+    return [(b, z) for b in TBX for z in zs] + [(0, 0, b, z) for b in TBX_FLUX_ONLY for z in zs]
+
+
+def _kernel_tile(entry, kernel):
+    """The (tbx, tzs) a table entry gives one kernel (0: trace, 1: flux), or
+    BUILTIN."""
+    if len(entry) == 2:
+        return tuple(entry)
+    return tuple(entry[2 * kernel:2 * kernel + 2])
 
 
 BUILTIN = (0, 0)  # table entry keeping a kernel's built-in tile
@@ -69,11 +83,13 @@ def _time_class(n, tiles, prm, nboxes, reps, torch):
 def _pick(t, kernel):
     """The fastest tile for one kernel (0: trace, 1: flux), kept only if it
     beats the built-in choice by MARGIN (timing noise must not replace a good
-    built-in tile with an equal one)."""
-    best = min(t, key=lambda k: t[k][kernel])
+    built-in tile with an equal one).  Entries that leave this kernel at its
+    built-in tile do not compete for it."""
+    own = [k for k in t if k == BUILTIN or _kernel_tile(k, kernel) != BUILTIN]
+    best = min(own, key=lambda k: t[k][kernel])
     if best != BUILTIN and t[best][kernel] < (1.0 - MARGIN) * t[BUILTIN][kernel]:
-        return best
-    return BUILTIN
+        return _kernel_tile(best, kernel), t[best][kernel]
+    return BUILTIN, t[BUILTIN][kernel]
 
 
 def tune(boxes, prm=None, max_boxes_per_class=4096, min_cells_per_class=2 ** 23, reps=3,
@@ -93,13 +109,13 @@ def tune(boxes, prm=None, max_boxes_per_class=4096, min_cells_per_class=2 ** 23,
         cells = n[0] * n[1] * n[2]
         nb = max(1, min(max_boxes_per_class, -(-min_cells_per_class // cells)))
         t = _time_class(n, [BUILTIN] + candidates(n), prm, nb, reps, torch)
-        b1, b2 = _pick(t, 0), _pick(t, 1)
+        (b1, ms1), (b2, ms2) = _pick(t, 0), _pick(t, 1)
         if (b1, b2) != (BUILTIN, BUILTIN):
             table[shape_key(n)] = (b1[0], b1[1], b2[0], b2[1])
-        timings[shape_key(n)] = {"%d,%d" % k: v for k, v in t.items()}
+        timings[shape_key(n)] = {",".join("%d" % x for x in k): v for k, v in t.items()}
         if log:
             log("tiles %s: trace %s (%.3f ms, built-in %.3f), flux %s (%.3f ms, built-in %.3f), "
-                "%d boxes" % (shape_key(n), b1, t[b1][0], t[BUILTIN][0], b2, t[b2][1],
+                "%d boxes" % (shape_key(n), b1, ms1, t[BUILTIN][0], b2, ms2,
                               t[BUILTIN][1], nb))
     return table, timings
 

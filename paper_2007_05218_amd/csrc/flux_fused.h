@@ -205,7 +205,7 @@ __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long n
 {
     Tile T;
     T.BX = g.tbx2;
-    T.BY = kFT / g.tbx2;
+    T.BY = flux_rows(g.tbx2);
     T.TX = T.BX - 2;
     T.TY = T.BY - 2;
     const int ntx = (g.n[0] + T.TX - 1) / T.TX;
@@ -229,7 +229,7 @@ __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long n
 }
 
 // x-neighbour exchange inside the wavefront: tile rows are runs of BX lanes
-// (BX divides 64), so a lane's low and high x-neighbours are lanes t-1 and
+// (whole rows in each wavefront), so a lane's low and high x-neighbours are lanes t-1 and
 // t+1 of its own wavefront, and a DPP shift of the whole wavefront by one
 // lane delivers their values with no LDS traffic and no barrier.  (A lane at
 // a row end receives another row's value or its own; nothing it computes
@@ -301,17 +301,29 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
     const WS &ws = o.ws;
     const Tile T = tile_of(g, o.blk, o.nblk);
     const int t = threadIdx.x;
-    const int tx = t % T.BX, ty = t / T.BX;
+    // lane -> column: each wavefront holds 64 / BX whole rows of BX lanes
+    // (the x-exchanges are shifts of the whole wavefront, so a row must not
+    // straddle two); lanes past the last whole row (BX = 18: lanes 54-63)
+    // are idle: they repeat the last row's last column, exchange with no
+    // neighbour and write nothing
+    const int rpw = 64 / T.BX, lw = t & 63;
+    const bool act = lw < rpw * T.BX;
+    const int tx = act ? lw % T.BX : T.BX - 1;
+    const int ty = (t >> 6) * rpw + (act ? lw / T.BX : rpw - 1);
+    auto lane_of = [&](int yy) { return (yy / rpw) * 64 + (yy % rpw) * T.BX + tx; };
     const int x = T.x0 - 1 + tx, y = T.y0 - 1 + ty;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
     // loads come from the clamped column (inside the traced region); results
     // of columns outside it are never used
     const int xc = min(x, n0), yc = min(y, n1);
-    const int tD = ty >= 1 ? t - T.BX : t, tU = ty + 1 < T.BY ? t + T.BX : t;
+    const int tD = act && ty >= 1 ? lane_of(ty - 1) : t;
+    const int tU = act && ty + 1 < T.BY ? lane_of(ty + 1) : t;
     // neighbour lanes present in the tile: a value that depends on an
     // exchange with a missing neighbour is never used and raises no error bit
-    const bool hL = tx >= 1, hR = tx + 1 < T.BX, hD = ty >= 1, hU = ty + 1 < T.BY;
-    const bool outc = tx >= 1 && tx <= T.TX && ty >= 1 && ty <= T.TY && x < n0 && y < n1;
+    const bool hL = act && tx >= 1, hR = act && tx + 1 < T.BX, hD = act && ty >= 1,
+               hU = act && ty + 1 < T.BY;
+    const bool outc =
+        act && tx >= 1 && tx <= T.TX && ty >= 1 && ty <= T.TY && x < n0 && y < n1;
 
     // region tests of the whole-box step (where it computes each quantity)
     const bool rx_f = inr(x, 0, n0), rx_fh = inr(x + 1, 0, n0), rx_c = inr(x, 0, n0 - 1),
@@ -347,7 +359,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         stb64((double *)fb, mfo, v);
     };
     unsigned exm = 0;
-    if (EX) {
+    if (EX && act) {
         const bool ex_x = inr(x, -1, n0), ex_y = inr(y, -1, n1);
         const bool fx = hL && rx_f, fy = hD && ry_f, cx = hL && hR && rx_c, cy = hD && hU && ry_c;
         exm = (unsigned)(fx && ex_y) << 0 | (unsigned)(fy && ex_x) << 1 |
@@ -585,7 +597,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         }
         putX(cz, 10, t, F3zq);
     }
-    if (err) atomicOr(err_dev, err);
+    if (err && act) atomicOr(err_dev, err);
     // (every lane has passed the z-march's last barrier, and the last reads
     // of ya happened before it: ya is free)
     if (o.dtn) block_dt_min(dtn, cfl, o.dtn, L.dtn_min, ya.v[0]);

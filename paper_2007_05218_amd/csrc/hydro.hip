@@ -66,6 +66,10 @@ struct Geo {
     int tbx1, tzs1, tbx2, tzs2;
 };
 
+// rows of a flux-kernel tile of width bx: 64 / bx whole rows per wavefront,
+// four wavefronts (bx = 18: three rows of 18 lanes each, twelve rows)
+__host__ __device__ constexpr int flux_rows(int bx) { return 4 * (64 / bx); }
+
 // workspace fields: traced face states (direction d, high/low face,
 // component v)
 __host__ __device__ constexpr int QHI(int d, int v) { return d * 10 + v; }
@@ -173,8 +177,8 @@ __host__ inline long long stage_blocks(const Geo &g, int st)
         return ((g.n[0] + 2 + TX - 1) / TX) * ((g.n[1] + 2 + TY - 1) / TY) *
                ((g.n[2] + 2 + g.tzs1 - 1) / g.tzs1);
     }
-    if (st == ST_FLUX) {  // tiles of (tbx-2) x (256/tbx-2) columns over [0, n)
-        const long long TX = g.tbx2 - 2, TY = 256 / g.tbx2 - 2;
+    if (st == ST_FLUX) {  // tiles of (tbx-2) x (rows-2) columns over [0, n)
+        const long long TX = g.tbx2 - 2, TY = flux_rows(g.tbx2) - 2;
         return ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) *
                ((g.n[2] + g.tzs2 - 1) / g.tzs2);
     }
@@ -469,7 +473,8 @@ bool flatten_ok(const hydro_params *p, const hydro_box *boxes, int nb)
 
 // Built-in tile choice for the fused kernels when no tuned table applies
 // (from a sweep on the 512^3 box): both kernels prefer square tiles
-// (16 x 16 columns); the trace kernel z-segments of 16-32 planes (more
+// (16 x 16 columns; the flux kernel rows of 18 where they cover a small box
+// with fewer tiles); the trace kernel z-segments of 16-32 planes (more
 // blocks, planes in flight kept in cache), the flux kernel up to 64 planes
 // (a segment costs it two warm-up planes).
 int default_zs(long long tiles, int nz, int zmax)
@@ -481,16 +486,38 @@ int default_zs(long long tiles, int nz, int zmax)
     return zs;
 }
 
+// flux-kernel tiles covering an n0 x n1 cross-section with rows of bx lanes
+long long flux_tiles(int bx, int n0, int n1)
+{
+    const long long tx = bx - 2, ty = flux_rows(bx) - 2;
+    return ((n0 + tx - 1) / tx) * ((n1 + ty - 1) / ty);
+}
+
 void set_default_tiles(Geo &g)
 {
     g.tbx1 = 16;
     g.tzs1 = default_zs((long long)((g.n[0] + 2 + 15) / 16) * ((g.n[1] + 2 + 15) / 16),
                         g.n[2] + 2, 32);
+    // the flux kernel: rows of 16 lanes, or of 18 where they cover the cross
+    // section with fewer tiles (every tile costs the same 256 lanes), as for
+    // boxes 16 or 32 cells wide; other widths are left to a tuned table
     g.tbx2 = 16;
-    g.tzs2 = default_zs((long long)((g.n[0] + 13) / 14) * ((g.n[1] + 13) / 14), g.n[2], 64);
+    long long tiles = flux_tiles(16, g.n[0], g.n[1]);
+    if (flux_tiles(18, g.n[0], g.n[1]) < tiles) {
+        g.tbx2 = 18;
+        tiles = flux_tiles(18, g.n[0], g.n[1]);
+    }
+    g.tzs2 = default_zs(tiles, g.n[2], 64);
 }
 
-bool tiles_valid(int tbx, int tzs) { return (tbx == 8 || tbx == 16 || tbx == 32) && tzs >= 1; }
+// tile widths: the trace kernel's 256 columns are tbx x 256/tbx; the flux
+// kernel's rows of tbx lanes fill each wavefront with 64/tbx whole rows (18:
+// three rows and ten idle lanes, for boxes 16 or 32 cells wide)
+bool trace_tile_valid(int tbx, int tzs) { return (tbx == 8 || tbx == 16 || tbx == 32) && tzs >= 1; }
+bool flux_tile_valid(int tbx, int tzs)
+{
+    return (tbx == 8 || tbx == 16 || tbx == 18 || tbx == 32) && tzs >= 1;
+}
 
 Geo make_geo(const hydro_box *b)
 {
@@ -647,9 +674,8 @@ bool parse_tiles(const char *js, std::vector<TileRule> &out)
         } else if (k != 4) {
             return false;
         }
-        for (int kk = 0; kk < 4; kk += 2)
-            if (!(r.t[kk] == 0 && r.t[kk + 1] == 0) && !tiles_valid(r.t[kk], r.t[kk + 1]))
-                return false;
+        if (!(r.t[0] == 0 && r.t[1] == 0) && !trace_tile_valid(r.t[0], r.t[1])) return false;
+        if (!(r.t[2] == 0 && r.t[3] == 0) && !flux_tile_valid(r.t[2], r.t[3])) return false;
         out.push_back(r);
         ws();
         if (*c == ',') {

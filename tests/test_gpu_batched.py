@@ -99,7 +99,8 @@ def test_tile_shapes_do_not_change_results(gpu):
     states, boxes, prm = inputs.level(nboxes=12, seed=8)
     shapes = {tuple(b["n"]) for b in boxes}
     res = []
-    for tb in [(8, 8), (16, 64), (32, 16, 8, 32), (16, 4, 32, 128)]:
+    for tb in [(8, 8), (16, 64), (32, 16, 8, 32), (16, 4, 32, 128), (16, 8, 18, 32),
+               (8, 16, 18, 4)]:
         table = {autotune.shape_key(n): tb for n in shapes}
         lev = gpu.Level(states, boxes, prm, shared_dt=True,
                         autotune_json=autotune.table_json(table))
@@ -112,6 +113,34 @@ def test_tile_shapes_do_not_change_results(gpu):
             assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box))
 
 
+def test_flux_rows_of_18_match_oracle(gpu, orc):
+    # flux tiles of 18-lane rows (three to a wavefront, ten idle lanes) on
+    # ragged boxes, 16 and 32 wide among them: the oracle's bits, and those
+    # of the built-in tiles
+    import torch
+    from paper_2007_05218_amd import autotune
+    shapes = [(16, 16, 16), (32, 16, 8), (17, 9, 20), (5, 33, 7), (4, 18, 4), (16, 40, 4)]
+    states, boxes = [], []
+    for i, n in enumerate(shapes):
+        U, b, prm = inputs.smooth(n, seed=40 + i, dx=(1.0 / 64,) * 3)
+        states.append(U)
+        boxes.append(b)
+    prm = dict(prm, grav=(0.0, -0.1, 0.05))
+    table = {autotune.shape_key(n): (0, 0, 18, z) for n, z in zip(shapes, (8, 3, 16, 2, 4, 1))}
+    res = []
+    for js in (None, autotune.table_json(table)):
+        lev = gpu.Level(states, boxes, prm, shared_dt=True, autotune_json=js)
+        lev.run(6)
+        torch.cuda.synchronize()
+        res.append((lev.states(), int(lev.err.item())))
+    os_, oerr = _oracle_level(orc, states, boxes, prm, 6)
+    assert res[1][1] == res[0][1] == oerr
+    for a, b, o, box in zip(res[0][0], res[1][0], os_, boxes):
+        assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box)), box["n"]
+        err, bw = compare(inputs.valid(b, box), inputs.valid(o, box))
+        assert err <= TOL and bw == 1.0, (box["n"], err, bw)
+
+
 def test_autotuner_runs(gpu):
     from paper_2007_05218_amd import autotune
     boxes = [inputs.box_desc((16, 32, 16)), inputs.box_desc((32, 16, 64))]
@@ -119,8 +148,8 @@ def test_autotuner_runs(gpu):
                                    reps=1)
     assert set(timings) == {"16x32x16", "32x16x64"} and set(table) <= set(timings)
     for k, (tbx1, tzs1, tbx2, tzs2) in table.items():
-        for tbx, tzs in ((tbx1, tzs1), (tbx2, tzs2)):
-            assert (tbx, tzs) == autotune.BUILTIN or (tbx in (8, 16, 32) and tzs >= 1)
+        assert (tbx1, tzs1) == autotune.BUILTIN or (tbx1 in (8, 16, 32) and tzs1 >= 1)
+        assert (tbx2, tzs2) == autotune.BUILTIN or (tbx2 in (8, 16, 18, 32) and tzs2 >= 1)
         assert (tbx1, tzs1, tbx2, tzs2) != autotune.BUILTIN * 2
     gpu.Plan(boxes, autotune.table_json(table)).close()
     # a table keeping one kernel's built-in tile is accepted

@@ -344,7 +344,7 @@ def test_tiled_species_level_graph_replay(gpu):
 
 def test_species_independent_of_tile_shapes(gpu):
     # the export's validity masks depend on the flux kernel's tile; species
-    # (and gas) results must not: 8-, 16- and 32-column tiles and several
+    # (and gas) results must not: 8-, 16-, 18- and 32-column tiles and several
     # z-segment lengths, batched, all give the same bits
     import torch
     from paper_2007_05218_amd import autotune
@@ -353,7 +353,8 @@ def test_species_independent_of_tile_shapes(gpu):
     S = [inputs.species(U, b, 2, seed=20 + i) for i, (U, b) in enumerate(zip(states, boxes))]
     shapes = {tuple(b["n"]) for b in boxes}
     res = []
-    for tb in [(16, 16, 16, 64), (32, 8, 8, 16), (8, 32, 32, 8), (16, 4, 8, 128)]:
+    for tb in [(16, 16, 16, 64), (32, 8, 8, 16), (8, 32, 32, 8), (16, 4, 8, 128),
+               (16, 16, 18, 32)]:
         table = {autotune.shape_key(n): tb for n in shapes}
         lev = gpu.Level(states, boxes, prm, shared_dt=True,
                         autotune_json=autotune.table_json(table), species=S)
