@@ -293,11 +293,11 @@ hydro_status hydro_fill_ghosts_level_species(int nb, double *const *S_ptrs_dev, 
 /* Plan for a fixed list of boxes: validates them, chooses the tile shapes
  * (autotune_json: NULL for the built-in choice, else a JSON object mapping
  * box shapes "NXxNYxNZ" to [tbx, tzs] for both fused kernels or
- * [tbx1, tzs1, tbx2, tzs2] for the trace and flux kernels: tile width tbx1
- * in {8,16,32} (tiles of tbx1 x 256/tbx1 columns), tbx2 in {8,16,18,32}
- * (rows of tbx2 lanes, 64/tbx2 whole rows per wavefront, four wavefronts;
- * the outer ring of columns supplies neighbours), z-segment length
- * tzs >= 1; a pair 0, 0 keeps that kernel's built-in tile; as written by
+ * [tbx1, tzs1, tbx2, tzs2] for the trace and flux kernels: tile width
+ * tbx in {8,16,18,32} (trace kernel: tiles of tbx1 x 256/tbx1 columns;
+ * flux kernel: rows of tbx2 lanes, 64/tbx2 whole rows per wavefront, four
+ * wavefronts, the outer ring of columns supplying neighbours), z-segment
+ * length tzs >= 1; a pair 0, 0 keeps that kernel's built-in tile; as written by
  * the package's autotuner) and builds the device work list.  *plan receives
  * an opaque handle.  HYDRO_EINVAL for an invalid box or table. */
 hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,

@@ -2,10 +2,10 @@
 
 The two fused kernels of the step (the trace kernel and the flux kernel)
 each process a box in tiles of columns marching over z-segments of tzs
-planes: the trace kernel tbx x 256/tbx columns (tbx in {8, 16, 32}), the
-flux kernel rows of tbx lanes, 64/tbx whole rows per wavefront (tbx in
-{8, 16, 18, 32}; 18 leaves ten lanes of each wavefront idle but fits boxes
-16 or 32 cells wide, whose 16-lane rows would compute 14 columns each).
+planes, tile width tbx in {8, 16, 18, 32}: the trace kernel tbx x 256/tbx
+columns, the flux kernel rows of tbx lanes, 64/tbx whole rows per
+wavefront (18 leaves threads idle but fits boxes 16 cells wide, and for
+the flux kernel 32, whose 16-lane rows would compute 14 columns each).
 The best tile depends on the box shape: narrow boxes waste halo columns in
 wide tiles, short boxes want short z-segments to expose enough blocks, tall
 ones long segments to amortise the two warm-up planes.  The paper finds the
@@ -22,8 +22,7 @@ import json
 
 from . import hydro, inputs
 
-TBX = (8, 16, 32)        # widths both kernels take
-TBX_FLUX_ONLY = (18,)     # widths only the flux kernel takes
+TBX = (8, 16, 18, 32)
 TZS = (8, 16, 32, 64, 128)
 STAGES = ("trace", "flux_update")
 
@@ -39,10 +38,9 @@ def table_json(table):
 
 
 def candidates(n):
-    """Table entries to time for shape n: (tbx, tzs) for both kernels, and
-    (0, 0, tbx, tzs) for the flux-only widths (the trace kernel built-in)."""
+    """Table entries to time for shape n: (tbx, tzs), for both kernels."""
     zs = sorted({z for z in TZS if z < n[2]} | {n[2]})
-    return [(b, z) for b in TBX for z in zs] + [(0, 0, b, z) for b in TBX_FLUX_ONLY for z in zs]
+    return [(b, z) for b in TBX for z in zs]
 
 
 def _kernel_tile(entry, kernel):

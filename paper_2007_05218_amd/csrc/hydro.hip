@@ -495,8 +495,13 @@ long long flux_tiles(int bx, int n0, int n1)
 
 void set_default_tiles(Geo &g)
 {
-    g.tbx1 = 16;
-    g.tzs1 = default_zs((long long)((g.n[0] + 2 + 15) / 16) * ((g.n[1] + 2 + 15) / 16),
+    // the trace kernel: 16 x 16 columns, or 32 x 8 for a box 15 to 30 cells
+    // wide (its traced columns in one tile row: the autotuner's choice for
+    // boxes 16 cells wide)
+    g.tbx1 = g.n[0] >= 15 && g.n[0] <= 30 ? 32 : 16;
+    const int by1 = 256 / g.tbx1;
+    g.tzs1 = default_zs((long long)((g.n[0] + 2 + g.tbx1 - 1) / g.tbx1) *
+                            ((g.n[1] + 2 + by1 - 1) / by1),
                         g.n[2] + 2, 32);
     // the flux kernel: rows of 16 lanes, or of 18 where they cover the cross
     // section with fewer tiles (every tile costs the same 256 lanes), as for
@@ -510,11 +515,11 @@ void set_default_tiles(Geo &g)
     g.tzs2 = default_zs(tiles, g.n[2], 64);
 }
 
-// tile widths: the trace kernel's 256 columns are tbx x 256/tbx; the flux
-// kernel's rows of tbx lanes fill each wavefront with 64/tbx whole rows (18:
-// three rows and ten idle lanes, for boxes 16 or 32 cells wide)
-bool trace_tile_valid(int tbx, int tzs) { return (tbx == 8 || tbx == 16 || tbx == 32) && tzs >= 1; }
-bool flux_tile_valid(int tbx, int tzs)
+// tile widths: the trace kernel's tiles are tbx x (256/tbx) columns (18: 18 x
+// 14, four threads idle); the flux kernel's
+// rows of tbx lanes fill each wavefront with 64/tbx whole rows (18: three
+// rows and ten idle lanes, for boxes 16 or 32 cells wide)
+bool tile_valid(int tbx, int tzs)
 {
     return (tbx == 8 || tbx == 16 || tbx == 18 || tbx == 32) && tzs >= 1;
 }
@@ -674,8 +679,9 @@ bool parse_tiles(const char *js, std::vector<TileRule> &out)
         } else if (k != 4) {
             return false;
         }
-        if (!(r.t[0] == 0 && r.t[1] == 0) && !trace_tile_valid(r.t[0], r.t[1])) return false;
-        if (!(r.t[2] == 0 && r.t[3] == 0) && !flux_tile_valid(r.t[2], r.t[3])) return false;
+        for (int kk = 0; kk < 4; kk += 2)
+            if (!(r.t[kk] == 0 && r.t[kk + 1] == 0) && !tile_valid(r.t[kk], r.t[kk + 1]))
+                return false;
         out.push_back(r);
         ws();
         if (*c == ',') {

@@ -23,7 +23,7 @@
 namespace {
 
 constexpr int kTT = 256;      // threads of a fused-trace block
-constexpr int kTPlane = 432;  // LDS cells of one plane: (BX+4)(BY+4) <= 432 for BX in {8,16,32}
+constexpr int kTPlane = 432;  // LDS cells of one plane: (BX+4)(BY+4) <= 432 for BX in {8,16,18,32}
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -74,7 +74,9 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     const int t = threadIdx.x;
     const int tx = t % BX, ty = t / BX;
     const int x = x0 + tx, y = y0 + ty;  // this thread's column
-    const bool inner = x <= n0 && y <= n1;
+    // (with BX = 18 the tile has 14 rows, 252 of the 256 threads; the other
+    // four only keep the block's barriers)
+    const bool inner = x <= n0 && y <= n1 && t < BX * BY;
     const int rc = (ty + 2) * RW + (tx + 2);  // own column in the plane buffer
     const unsigned wo = ws.off(inner ? x : n0, inner ? y : n1);  // own column in the workspace
 

@@ -136,8 +136,8 @@ def test_status_strings():
                                 '{"16x16": [16, 8]}', '["16x16x16"]', '{"16x16x16": [16, 8]} x',
                                 '{"16x16x16": [16, 8, 32]}', '{"16x16x16": [16, 8, 32, 8, 8]}',
                                 '{"16x16x16": [16, 8, 24, 8]}', '{"16x16x16": [16, 8, 0, 8]}',
-                                '{"16x16x16": [0, 4, 16, 8]}', '{"16x16x16": [18, 8]}',
-                                '{"16x16x16": [18, 8, 16, 8]}', '{"16x16x16": [16, 8, 20, 8]}'])
+                                '{"16x16x16": [0, 4, 16, 8]}', '{"16x16x16": [20, 8]}',
+                                '{"16x16x16": [18, 0, 16, 8]}', '{"16x16x16": [16, 8, 20, 8]}'])
 def test_plan_rejects_bad_tile_tables(js):
     # the table is parsed before any device allocation, so this needs no GPU
     L = hydro.lib()
@@ -151,10 +151,9 @@ def test_autotune_table_format():
     js = autotune.table_json({"16x32x64": (16, 32), "64x64x64": (32, 64, 16, 32)})
     assert js == '{"16x32x64": [16, 32], "64x64x64": [32, 64, 16, 32]}'
     c = autotune.candidates((16, 32, 64))
-    assert (8, 64) in c and (32, 8) in c and (0, 0, 18, 64) in c
-    # both kernels take widths 8, 16, 32; only the flux kernel takes 18
-    assert all(t[0] in (8, 16, 32) for t in c if len(t) == 2)
-    assert all(t[:2] == (0, 0) and t[2] == 18 for t in c if len(t) == 4)
+    assert (8, 64) in c and (32, 8) in c and (18, 64) in c
+    assert all(t[0] in (8, 16, 18, 32) for t in c)
+    # a four-entry tile gives each kernel its own pair
     assert autotune._kernel_tile((0, 0, 18, 8), 0) == autotune.BUILTIN
     assert autotune._kernel_tile((0, 0, 18, 8), 1) == (18, 8)
     assert autotune._kernel_tile((16, 8), 1) == (16, 8)

@@ -354,7 +354,7 @@ def test_species_independent_of_tile_shapes(gpu):
     shapes = {tuple(b["n"]) for b in boxes}
     res = []
     for tb in [(16, 16, 16, 64), (32, 8, 8, 16), (8, 32, 32, 8), (16, 4, 8, 128),
-               (16, 16, 18, 32)]:
+               (18, 16, 18, 32)]:
         table = {autotune.shape_key(n): tb for n in shapes}
         lev = gpu.Level(states, boxes, prm, shared_dt=True,
                         autotune_json=autotune.table_json(table), species=S)
