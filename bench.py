@@ -458,7 +458,10 @@ def time_serving(torch, inputs, nreq, warm, nstates, seed=3):
     ex = GpuExecutor(max_active=64)
     srv = Server(ex, budget_bytes=200e9, max_active=64)
     t0 = time.perf_counter()
+    # (a ROCTx range around the measured loop, for API traces of it)
+    torch.cuda.nvtx.range_push("serve loop")
     srv.run(specs)
+    torch.cuda.nvtx.range_pop()
     wall = time.perf_counter() - t0
     ex.close()
     m = srv.metrics(skip=warm)
