@@ -113,7 +113,8 @@ def test_tile_shapes_do_not_change_results(gpu):
             assert np.array_equal(inputs.valid(a, box), inputs.valid(b, box))
 
 
-def test_flux_rows_of_18_match_oracle(gpu, orc):
+@pytest.mark.parametrize("flatten", [0, 1])
+def test_flux_rows_of_18_match_oracle(gpu, orc, flatten):
     # tiles 18 columns wide for both kernels (the trace kernel's 18 x 14 with
     # four idle threads, the flux kernel's rows of 18 lanes, three to a
     # wavefront, ten idle lanes) on ragged boxes, 16 and 32 wide among them:
@@ -126,7 +127,7 @@ def test_flux_rows_of_18_match_oracle(gpu, orc):
         U, b, prm = inputs.smooth(n, seed=40 + i, dx=(1.0 / 64,) * 3)
         states.append(U)
         boxes.append(b)
-    prm = dict(prm, grav=(0.0, -0.1, 0.05))
+    prm = dict(prm, grav=(0.0, -0.1, 0.05), flatten=flatten)
     table = {autotune.shape_key(n): (18, z, 18, z) for n, z in zip(shapes, (8, 3, 16, 2, 4, 1))}
     res = []
     for js in (None, autotune.table_json(table)):
