@@ -18,7 +18,10 @@ Also reported on the same JSON line:
                 second figure; per kernel also its HBM rates (algorithmic
                 bytes and the committed FETCH_SIZE + WRITE_SIZE counters, per
                 launch, over its time) against 8 TB/s and the practical roof
-                of a plain copy kernel timed in the same run
+                of a plain copy kernel timed in the same run; and, from the
+                committed counters, the instructions each kernel executed and
+                the step's cell-updates/s against the roof its FP64 VALU
+                instructions set
   cpu_baseline  the CPU oracle timed on the host on a bounded sample of the
                 same workload (rank 0, N = 1 only), with the CPU model and
                 one-thread rates on the Sod 32^3 tube and the KH box at 64^3
@@ -33,6 +36,7 @@ Also reported on the same JSON line:
                 saturated capacity batched vs one request at a time)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workloads ...]
+(defaults: 50 timed steps after 3 warm-up steps, every workload)
 """
 import argparse
 import json
@@ -123,7 +127,7 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workloads", default="rt512,kh256,species,sedov,level,serve",
                     help="comma list of rt512, kh256, sedov, level, serve, copy (a plain 2 GiB "
