@@ -42,7 +42,9 @@ __device__ __forceinline__ double flat_axis(const double (&p)[7], const double (
 // pressures and in-plane velocities, on the tile plus a three-cell ring, are
 // converted from U once into LDS (the x and y pencils read them there); each
 // column carries its own z-pencil (pressure and normal velocity of the
-// planes z-3 .. z+3) in registers, converting one new plane ahead per step.
+// planes z-3 .. z+3) in registers.  The conserved values of the next plane
+// (the thread's ring cells and its column's cell three planes ahead) are
+// fetched one z-step ahead, so their latency overlaps the current plane.
 constexpr int kFlW = kFlB + 6;
 
 __global__ void __launch_bounds__(kBlock) k_flatten(Launch L, double gamma)
@@ -63,36 +65,61 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Launch L, double gamma)
     const int x = x0 + tx, y = y0 + ty;
     const bool inner = x <= n0 && y <= n1;
     const double gm1 = gamma - 1.0;
-    const double *U = o.U;
-    // primitives of a cell, its coordinates clamped into the ghosted box
-    // (clamped cells only feed lanes whose results are not stored)
-    auto prim_at = [&](int i, int j, int k) {
+    // byte offset of a cell, its coordinates clamped into the ghosted box
+    // (clamped cells only feed lanes whose results are not stored; one
+    // component of a box is below 2 GiB)
+    auto off_at = [&](int i, int j, int k) {
         i = min(max(i, -ng), n0 + ng - 1);
         j = min(max(j, -ng), n1 + ng - 1);
         k = min(max(k, -ng), n2 + ng - 1);
-        const long long c = cell(g, i, j, k);
-        return prim_of(U[c], U[g.cs + c], U[2 * g.cs + c], U[3 * g.cs + c], U[4 * g.cs + c], gm1);
+        return (unsigned)cell(g, i, j, k) * 8u;
+    };
+    auto load5 = [&](unsigned bo, double (&c)[5]) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) c[v] = ldb(o.U + v * g.cs, bo);
+    };
+    auto prim5 = [&](const double (&c)[5]) { return prim_of(c[0], c[1], c[2], c[3], c[4], gm1); };
+    // the ring cells of a plane this thread converts: t and t + 256 (of 484)
+    constexpr int kRing = kFlW * kFlW;
+    static_assert(kRing <= 2 * kBlock, "two ring cells per thread");
+    const int r1 = t + kBlock;
+    const bool has1 = r1 < kRing;
+    const int rx0 = x0 - 3 + t % kFlW, ry0 = y0 - 3 + t / kFlW;
+    const int rx1 = x0 - 3 + r1 % kFlW, ry1 = y0 - 3 + r1 / kFlW;
+    double c0[5], c1[5], cz[5];  // next plane: ring cells, own column's cell
+    auto fetch = [&](int z) {
+        load5(off_at(rx0, ry0, z), c0);
+        if (has1) load5(off_at(rx1, ry1, z), c1);
+        load5(off_at(x, y, z + 3), cz);
     };
     // own column's z-pencil: pressure and z-velocity of planes z-3 .. z+3
     double zp[7], zw[7];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
-        const Prim q = prim_at(x, y, z0 - 3 + m);
+        double c[5];
+        load5(off_at(x, y, z0 - 3 + m), c);
+        const Prim q = prim5(c);
         zp[m] = q.p;
         zw[m] = q.w;
     }
+    fetch(z0);
     for (int z = z0; z < z1; ++z) {
         {
-            const Prim q = prim_at(x, y, z + 3);
+            Prim q = prim5(c0);
+            sp[t] = q.p;
+            su[t] = q.u;
+            sv[t] = q.v;
+            if (has1) {
+                q = prim5(c1);
+                sp[r1] = q.p;
+                su[r1] = q.u;
+                sv[r1] = q.v;
+            }
+            q = prim5(cz);
             zp[6] = q.p;
             zw[6] = q.w;
         }
-        for (int r = t; r < kFlW * kFlW; r += kBlock) {
-            const Prim q = prim_at(x0 - 3 + r % kFlW, y0 - 3 + r / kFlW, z);
-            sp[r] = q.p;
-            su[r] = q.u;
-            sv[r] = q.v;
-        }
+        if (z + 1 < z1) fetch(z + 1);
         __syncthreads();
         const int rc = (ty + 3) * kFlW + (tx + 3);
         double px[7], ux[7], py[7], vy[7];

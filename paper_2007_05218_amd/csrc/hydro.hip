@@ -426,8 +426,8 @@ __global__ void __launch_bounds__(kBlock) k_dt(Launch L, double gamma, double cf
     block_dt_min(m, cfl, dt_bits + o.b, dtmin_bits, part);
 }
 
-#include "flatten.h"
 #include "flux_fused.h"
+#include "flatten.h"
 #include "trace_fused.h"
 #include "species.h"
 #include "species_fused.h"
