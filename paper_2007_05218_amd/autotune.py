@@ -4,8 +4,10 @@ The two fused kernels of the step (the trace kernel and the flux kernel)
 each process a box in tiles of columns marching over z-segments of tzs
 planes, tile width tbx in {8, 16, 18, 32}: the trace kernel tbx x 256/tbx
 columns, the flux kernel rows of tbx lanes, 64/tbx whole rows per
-wavefront (18 leaves threads idle but fits boxes 16 cells wide, and for
-the flux kernel 32, whose 16-lane rows would compute 14 columns each).
+wavefront.  Width 18 leaves threads idle, but a flux-kernel row of 18 lanes
+computes 16 columns, so it covers a box 16 cells wide with one tile row and
+one 32 cells wide with two, where rows of 16 lanes (14 columns each) need
+two and three.
 The best tile depends on the box shape: narrow boxes waste halo columns in
 wide tiles, short boxes want short z-segments to expose enough blocks, tall
 ones long segments to amortise the two warm-up planes.  The paper finds the
