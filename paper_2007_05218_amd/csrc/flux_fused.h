@@ -228,10 +228,11 @@ __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long n
     return T;
 }
 
-// x-neighbour exchange inside the wavefront: tile rows are runs of BX lanes
-// (whole rows in each wavefront), so a lane's low and high x-neighbours are lanes t-1 and
-// t+1 of its own wavefront, and a DPP shift of the whole wavefront by one
-// lane delivers their values with no LDS traffic and no barrier.  (A lane at
+// x-neighbour exchange inside the wavefront: tile rows are runs of BX lanes,
+// whole rows in each wavefront, so a lane's low and high x-neighbours are
+// lanes t-1 and t+1 of its own wavefront, and a DPP shift of the whole
+// wavefront by one lane delivers their values with no LDS traffic and no
+// barrier.  (A lane at
 // a row end receives another row's value or its own; nothing it computes
 // from it is used.)
 // (bound_ctrl: the lane at the wavefront's end, which has no source lane,
