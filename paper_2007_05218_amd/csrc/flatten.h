@@ -54,13 +54,24 @@ __global__ void __launch_bounds__(kBlock) k_flatten(Launch L, double gamma)
     const Geo &g = o.g;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2], ng = g.ng;
     const int ntx = (n0 + 2 + kFlB - 1) / kFlB, nty = (n1 + 2 + kFlB - 1) / kFlB;
-    long long tt = o.blk;
+    // blocks are dealt to the 8 XCDs round-robin: give each XCD a contiguous
+    // run of tiles, so neighbouring tiles, which read each other's ring
+    // cells, share that XCD's L2
+    long long tt;
+    {
+        const long long per = o.nblk / 8, rem = o.nblk % 8;
+        const long long xx = o.blk % 8, ii = o.blk / 8;
+        tt = xx * per + (xx < rem ? xx : rem) + ii;
+    }
     const int ix = (int)(tt % ntx);
     tt /= ntx;
     const int iy = (int)(tt % nty);
     const int iz = (int)(tt / nty);
     const int x0 = -1 + ix * kFlB, y0 = -1 + iy * kFlB;
-    const int z0 = -1 + iz * kFlZ, z1 = min(n2 + 1, z0 + kFlZ);
+    // the traced planes [-1, n2+1) in equal z-segments (as many as planes of
+    // kFlZ need), each marched by one block
+    const int nseg = (n2 + 2 + kFlZ - 1) / kFlZ, seg = (n2 + 2 + nseg - 1) / nseg;
+    const int z0 = -1 + iz * seg, z1 = min(n2 + 1, z0 + seg);
     const int t = threadIdx.x, tx = t % kFlB, ty = t / kFlB;
     const int x = x0 + tx, y = y0 + ty;
     const bool inner = x <= n0 && y <= n1;
