@@ -159,6 +159,21 @@ def test_autotune_table_format():
     assert autotune._kernel_tile((16, 8), 1) == (16, 8)
 
 
+def test_autotune_pick_keeps_builtin_unless_clearly_faster():
+    # timings {entry: (trace ms, flux ms)}: each kernel takes its fastest
+    # entry only when it beats the built-in tile by the margin, and an entry
+    # that leaves a kernel at its built-in tile does not compete for it
+    from paper_2007_05218_amd import autotune
+    B = autotune.BUILTIN
+    t = {B: (1.00, 2.00), (16, 8): (0.99, 1.50), (32, 8): (0.80, 2.10),
+         (0, 0, 18, 16): (0.50, 1.40)}
+    assert autotune._pick(t, 0) == ((32, 8), 0.80)   # 20 % faster trace
+    assert autotune._pick(t, 1) == ((18, 16), 1.40)  # flux-only entry wins the flux
+    t = {B: (1.00, 2.00), (16, 8): (0.98, 1.99)}     # within the margin
+    assert autotune._pick(t, 0) == (B, 1.00)
+    assert autotune._pick(t, 1) == (B, 2.00)
+
+
 def _level_args(layout):
     """(boxes, lo, dom, bc_lo, bc_hi) of a tiling, possibly broken."""
     boxes = [inputs.box_desc(n) for n in layout["n"]]
