@@ -375,6 +375,9 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
     // plane-to-plane carries (values of the previous plane)
     // (zero until the first plane has been processed; the values derived from
     // them in the first two planes of a segment are never used)
+    // (the three states are carried without their 1/rho, which the solve
+    // re-forms from the carried density as 1/rho: six fewer registers held
+    // through the z-march, fewer spilled)
     Face c_zx_hi = {}, c_zy_hi = {}, fz_hi = {};  // corner (z|x), (z|y), final z: high face
     Flux F2zx = {}, F2zy = {};    // (z|x), (z|y) fluxes through the plane's low z-face
     int err = 0;
@@ -466,18 +469,20 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         {
             Face l = corner_state(qz_lo, dF1x, fx3, gm1, igm1, fb);  // (z|x)
             if (fb && hL && hR && rz_f && rx_c && ry_w) err |= fb;
-            Flux Fzx = hllc(c_zx_hi, l, 2, gamma, igm1);
+            Flux Fzx = hllc(with_ri(c_zx_hi), l, 2, gamma, igm1);
             if (exb(7) && q >= T.z0 && rz_f) mf_put(7, q, Fzx.m);
             Face h = corner_state(qz_hi, dF1x, fx3, gm1, igm1, fb);
             if (fb && hL && hR && rz_fh && rx_c && ry_w) err |= fb;
             c_zx_hi = h;
+            c_zx_hi.ri = 0.0;
             l = corner_state(qz_lo, dF1y, fy3, gm1, igm1, fb);  // (z|y)
             if (fb && hD && hU && rz_f && ry_c && rx_w) err |= fb;
-            Flux Fzy = hllc(c_zy_hi, l, 2, gamma, igm1);
+            Flux Fzy = hllc(with_ri(c_zy_hi), l, 2, gamma, igm1);
             if (exb(8) && q >= T.z0 && rz_f) mf_put(8, q, Fzy.m);
             h = corner_state(qz_hi, dF1y, fy3, gm1, igm1, fb);
             if (fb && hD && hU && rz_fh && ry_c && rx_w) err |= fb;
             c_zy_hi = h;
+            c_zy_hi.ri = 0.0;
             // z-differences of the (z|s) fluxes of plane q-1
             dzx = fdiff(Fzx, F2zx);
             dzy = fdiff(Fzy, F2zy);
@@ -493,9 +498,10 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         if (fb && zin && rz_f) err |= fb;
         Face zh = final_state2(qz_hi, dxy, dyx, fx2, fy2, gm1, igm1, fb);
         if (fb && zin && rz_fh) err |= fb;
-        const Flux F3zq = hllc(fz_hi, zl, 2, gamma, igm1);
+        const Flux F3zq = hllc(with_ri(fz_hi), zl, 2, gamma, igm1);
         if (exb(11) && q >= T.z0 && rz_f) mf_put(11, q, F3zq.m);
         fz_hi = zh;
+        fz_hi.ri = 0.0;
         // y-difference of the (y|z) fluxes of plane q (used next plane)
         const Flux dyz = fdiff(getX(yb.v, 5, tU), getX(yb.v, 5, t));
         // final x and y states of plane q-1
