@@ -132,7 +132,7 @@ __device__ __forceinline__ gchar *opaque_plane(const char *p)
 __device__ __forceinline__ Face load_face_b(gchar *pp, unsigned lo, int f0)
 {
     auto ld = [&](int f) {
-        return *(const __attribute__((address_space(1))) double *)(pp + lo + f * (kXB * 8));
+        return *(const __attribute__((address_space(1))) double *)(pp + lo + ws_foff(f));
     };
     Face f;
     f.r = ld(f0 + 0);

@@ -76,6 +76,12 @@ __host__ __device__ constexpr int QHI(int d, int v) { return d * 10 + v; }
 __host__ __device__ constexpr int QLO(int d, int v) { return d * 10 + 5 + v; }
 constexpr int kFields = 30;
 constexpr int kXB = 16;  // cells of an x-block of the workspace
+// byte offset of field f within a cell's slot of an x-block run (the cell's
+// own offset is 16 bytes per cell): pair (axis, component), then face
+__host__ __device__ constexpr int ws_foff(int f)
+{
+    return ((f / 10) * 5 + f % 5) * (kXB * 16) + ((f % 10) / 5) * 8;
+}
 
 // stages (block-count prefix arrays are kept per stage)
 enum { ST_FILL = 0, ST_DT = 1, ST_TRACE = 2, ST_FLUX = 3, ST_FLAT = 4, ST_COUNT = 5 };
@@ -97,12 +103,16 @@ __device__ __forceinline__ long long stride(const Geo &g, int d)
 // y in [-1, n1], z in [-2, n2+1] (the traced region plus one plane on each
 // side that the flux kernel's first and last z-steps read and never use).
 // Plane by plane, row by row, each run of 16 cells of a row (x-block) keeps
-// its 30 fields together: field f of the run is the 16 doubles (one 128-byte
-// line) at f*128 bytes from the run's start.  A lane's 30 fields are then one
+// its 30 fields together, as 15 pairs: the high- and low-face states of one
+// component along one axis.  Pair k of the run is 16 cells x 16 bytes (two
+// 128-byte lines) at k*256 bytes from the run's start, a cell's high-face
+// value first, its low-face value beside it.  A lane's 30 fields are then one
 // per-lane offset plus constant offsets from a per-plane base (no address
-// register per field), and the streams a kernel writes or reads at once are
+// register per field); the streams a kernel writes or reads at once are
 // neighbouring lines instead of 30 arrays a large power of two apart, which
-// land on the same memory channels.
+// land on the same memory channels; and the two states of a pair, which the
+// kernels store and load together, move as one 16-byte access (half the
+// memory instructions of one field per access).
 __host__ __device__ __forceinline__ int ws_xblocks(int n0) { return (n0 + 2 + kXB - 1) / kXB; }
 __host__ __device__ __forceinline__ long long ws_pitch(int n0, int n1)  // bytes per plane
 {
@@ -128,13 +138,13 @@ struct WS {
     {
         const unsigned X = (unsigned)(x + 1);
         return ((unsigned)(y + 1) * (unsigned)nxb + (X / kXB)) * (unsigned)(kFields * kXB * 8) +
-               (X % kXB) * 8u;
+               (X % kXB) * 16u;
     }
 };
 // field f of the column at byte offset lo of plane pointer pp
 __device__ __forceinline__ double ws_ld(const char *pp, unsigned lo, int f)
 {
-    return *(const double *)((pp + (size_t)lo) + f * (kXB * 8));
+    return *(const double *)((pp + (size_t)lo) + ws_foff(f));
 }
 __device__ __forceinline__ void ws_st(const char *pp, unsigned lo, int f, double v)
 {
@@ -142,7 +152,7 @@ __device__ __forceinline__ void ws_st(const char *pp, unsigned lo, int f, double
     // is read back by the next kernel, not this one)
     __builtin_nontemporal_store(
         v, (__attribute__((address_space(1))) double *)((const_cast<char *>(pp) + (size_t)lo) +
-                                                        f * (kXB * 8)));
+                                                        ws_foff(f)));
 }
 
 struct Reg {
