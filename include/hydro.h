@@ -297,7 +297,8 @@ hydro_status hydro_fill_ghosts_level_species(int nb, double *const *S_ptrs_dev, 
  * tbx in {8,16,18,32} (trace kernel: tiles of tbx1 x 256/tbx1 columns;
  * flux kernel: rows of tbx2 lanes, 64/tbx2 whole rows per wavefront, four
  * wavefronts, the outer ring of columns supplying neighbours), z-segment
- * length tzs >= 1; a pair 0, 0 keeps that kernel's built-in tile; as written by
+ * length tzs >= 1 (at most: a box's planes are split into equal segments no
+ * longer than tzs); a pair 0, 0 keeps that kernel's built-in tile; as written by
  * the package's autotuner) and builds the device work list.  *plan receives
  * an opaque handle.  HYDRO_EINVAL for an invalid box or table. */
 hydro_status hydro_plan_create(const hydro_box *boxes, int nb, const char *autotune_json,

@@ -223,8 +223,9 @@ __device__ __forceinline__ Tile tile_of(const Geo &g, long long blk, long long n
     const int iz = (int)(t / nty);
     T.x0 = ix * T.TX;
     T.y0 = iy * T.TY;
-    T.z0 = iz * g.tzs2;
-    T.z1 = min(g.n[2], T.z0 + g.tzs2);
+    const int zs = seg_len(g.n[2], g.tzs2);
+    T.z0 = iz * zs;
+    T.z1 = min(g.n[2], T.z0 + zs);
     return T;
 }
 

@@ -70,6 +70,14 @@ struct Geo {
 // four wavefronts (bx = 18: three rows of 18 lanes each, twelve rows)
 __host__ __device__ constexpr int flux_rows(int bx) { return 4 * (64 / bx); }
 
+// z-segments of a kernel over N planes with at most zs planes each, made
+// equal: ceil(N / zs) segments of ceil(N / segments) planes (the last may be
+// shorter; none is empty)
+__host__ __device__ constexpr int seg_len(int N, int zs)
+{
+    return (N + (N + zs - 1) / zs - 1) / ((N + zs - 1) / zs);
+}
+
 // workspace fields: traced face states (direction d, high/low face,
 // component v)
 __host__ __device__ constexpr int QHI(int d, int v) { return d * 10 + v; }
@@ -486,7 +494,9 @@ bool flatten_ok(const hydro_params *p, const hydro_box *boxes, int nb)
 // (16 x 16 columns; the flux kernel rows of 18 where they cover a small box
 // with fewer tiles); the trace kernel z-segments of 16-32 planes (more
 // blocks, planes in flight kept in cache), the flux kernel up to 64 planes
-// (a segment costs it two warm-up planes).
+// (a segment costs it two warm-up planes).  Either kernel splits a box's
+// planes into segments of equal length no longer than the chosen one (a box
+// 16 planes tall traces its 18 planes as 9 + 9, not 16 + 2).
 int default_zs(long long tiles, int nz, int zmax)
 {
     long long nzs = (8192 + tiles - 1) / tiles;  // aim at >= 8192 blocks (32 per CU)
@@ -505,10 +515,10 @@ long long flux_tiles(int bx, int n0, int n1)
 
 void set_default_tiles(Geo &g)
 {
-    // the trace kernel: 16 x 16 columns, or 32 x 8 for a box 15 to 30 cells
-    // wide (its traced columns in one tile row: the autotuner's choice for
-    // boxes 16 cells wide)
-    g.tbx1 = g.n[0] >= 15 && g.n[0] <= 30 ? 32 : 16;
+    // the trace kernel: 16 x 16 columns; for a box 15 to 30 cells wide, its
+    // 17 to 32 traced columns in one tile row: 18 x 14 (15 or 16 cells, the
+    // autotuner's choice for such boxes) or 32 x 8
+    g.tbx1 = g.n[0] >= 15 && g.n[0] <= 16 ? 18 : (g.n[0] >= 17 && g.n[0] <= 30 ? 32 : 16);
     const int by1 = 256 / g.tbx1;
     g.tzs1 = default_zs((long long)((g.n[0] + 2 + g.tbx1 - 1) / g.tbx1) *
                             ((g.n[1] + 2 + by1 - 1) / by1),
@@ -814,8 +824,8 @@ hydro_status plan_build(Plan *P, const hydro_box *boxes, int nb)
         for (int b = 0; b < nb; ++b) o[b] = b;
         auto zlen = [&](int b) {
             const Geo &g = P->geos[b];
-            if (s == ST_FLUX) return g.tzs2 < g.n[2] ? g.tzs2 : g.n[2];
-            if (s == ST_TRACE) return g.tzs1 < g.n[2] + 2 ? g.tzs1 : g.n[2] + 2;
+            if (s == ST_FLUX) return seg_len(g.n[2], g.tzs2);
+            if (s == ST_TRACE) return seg_len(g.n[2] + 2, g.tzs1);
             return 0;
         };
         std::stable_sort(o, o + nb, [&](int a, int b) { return zlen(a) > zlen(b); });

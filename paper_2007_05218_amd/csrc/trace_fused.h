@@ -69,7 +69,8 @@ k_trace_fused(Launch L, double gamma, double gx, double gy, double gz)
     const int iy = (int)(tt % nty);
     const int iz = (int)(tt / nty);
     const int x0 = -1 + ix * BX, y0 = -1 + iy * BY;
-    const int z0 = -1 + iz * g.tzs1, z1 = min(n2 + 1, z0 + g.tzs1);
+    const int zs = seg_len(n2 + 2, g.tzs1);
+    const int z0 = -1 + iz * zs, z1 = min(n2 + 1, z0 + zs);
 
     const int t = threadIdx.x;
     const int tx = t % BX, ty = t / BX;
