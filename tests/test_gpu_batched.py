@@ -143,6 +143,46 @@ def test_flux_rows_of_18_match_oracle(gpu, orc, flatten):
         assert err <= TOL and bw == 1.0, (box["n"], err, bw)
 
 
+def _seg_split(N, zs):
+    # the kernels' z-segments of N planes, no longer than zs, made equal
+    m = -(-N // zs)
+    seg = -(-N // m)
+    return [min(seg, N - i * seg) for i in range(m)]
+
+
+@pytest.mark.parametrize("flatten", [0, 1])
+def test_equal_z_segments_match_oracle(gpu, orc, flatten):
+    # segment lengths that do not divide a box's planes: both kernels split
+    # the planes into equal segments no longer than the length asked for
+    # (trace kernel: the n2 + 2 traced planes; flux kernel: the n2 planes),
+    # one plane per segment, and one segment for the whole box
+    import torch
+    from paper_2007_05218_amd import autotune
+    cases = [((20, 18, 30), (16, 20, 16, 20)),   # trace 32 -> 16 + 16, flux 30 -> 15 + 15
+             ((17, 21, 23), (16, 7, 18, 5)),     # 25 -> 7 7 7 4, 23 -> 5 5 5 5 3
+             ((9, 12, 13), (8, 1, 16, 1)),       # a plane per segment
+             ((14, 10, 11), (32, 64, 8, 64)),    # one segment
+             ((16, 16, 16), (18, 17, 18, 9))]    # 18 -> 9 + 9, 16 -> 8 + 8
+    for n, t in cases:
+        assert _seg_split(n[2] + 2, t[1]) and _seg_split(n[2], t[3])
+    states, boxes = [], []
+    for i, (n, _) in enumerate(cases):
+        U, b, prm = inputs.smooth(n, seed=70 + i, dx=(1.0 / 64,) * 3)
+        states.append(U)
+        boxes.append(b)
+    prm = dict(prm, grav=(0.02, 0.0, -0.1), flatten=flatten)
+    table = {autotune.shape_key(n): t for n, t in cases}
+    lev = gpu.Level(states, boxes, prm, shared_dt=True, autotune_json=autotune.table_json(table))
+    lev.run(5)
+    torch.cuda.synchronize()
+    g, gerr = lev.states(), int(lev.err.item())
+    os_, oerr = _oracle_level(orc, states, boxes, prm, 5)
+    assert gerr == oerr
+    for a, o, box in zip(g, os_, boxes):
+        err, bw = compare(inputs.valid(a, box), inputs.valid(o, box))
+        assert err <= TOL and bw == 1.0, (box["n"], err, bw)
+
+
 def test_autotuner_runs(gpu):
     from paper_2007_05218_amd import autotune
     boxes = [inputs.box_desc((16, 32, 16)), inputs.box_desc((32, 16, 64))]
