@@ -392,29 +392,32 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         // covers them)
         const bool rz_c = inr(q, 0, n2 - 1) && q >= T.z0, rz_w = inr(q, -1, n2);
         // ---------------------------------------------------- loads
-        // (the high y-state first: its exchange opens the z-step, and the
-        // other loads complete while the block meets at the barrier)
+        // (all issued before the first wait: the next plane's low z-state,
+        // which no other load's wait then holds back, and the high y-state,
+        // whose exchange opens the z-step; the other loads complete while
+        // the block meets at the barrier)
+        const Face qz_lo_n = load_face_b(opaque_plane(ws.plane(q + 1)), wo, QLO(2, 0));  // next plane
         const Face qy_hi = load_face_b(pq, wo, QHI(1, 0));
         putF(ya.v, 0, t, qy_hi);
         const Face qx_lo = load_face_b(pq, wo, QLO(0, 0)), qx_hi = load_face_b(pq, wo, QHI(0, 0));
         const Face qy_lo = load_face_b(pq, wo, QLO(1, 0));
         const Face qz_lo = load_face_b(pq, wo, QLO(2, 0)), qz_hi = load_face_b(pq, wo, QHI(2, 0));
-        const Face qz_lo_n = load_face_b(opaque_plane(ws.plane(q + 1)), wo, QLO(2, 0));  // next plane
         __syncthreads();
         // ---------------------------------------------------- round-1 fluxes
         // through each lane's low x/y faces (the low neighbour's high state
         // from the neighbour lane: x in the wavefront, y through LDS) and
         // through the plane's high z-face; their differences over the cell
-        const Flux F1zn = hllc(with_ri(qz_hi), with_ri(qz_lo_n), 2, gamma, igm1);
-        if (exb(2) && inr(q + 1, 0, n2)) mf_put(2, q + 1, F1zn.m);
-        const Flux F1x = hllc(prevF(with_ri(qx_hi)), with_ri(qx_lo), 0, gamma, igm1);
-        if (exb(0) && rz_w) mf_put(0, q, F1x.m);
-        const Flux dF1x = next_minus(F1x);
+        // (solved in the order their loads complete: y, x, then z)
         {
             const Flux F1y = hllc(getF(ya.v, 0, tD), with_ri(qy_lo), 1, gamma, igm1);
             putX(yb.v, 0, t, F1y);
             if (exb(1) && rz_w) mf_put(1, q, F1y.m);
         }
+        const Flux F1x = hllc(prevF(with_ri(qx_hi)), with_ri(qx_lo), 0, gamma, igm1);
+        if (exb(0) && rz_w) mf_put(0, q, F1x.m);
+        const Flux dF1x = next_minus(F1x);
+        const Flux F1zn = hllc(with_ri(qz_hi), with_ri(qz_lo_n), 2, gamma, igm1);
+        if (exb(2) && inr(q + 1, 0, n2)) mf_put(2, q + 1, F1zn.m);
         // (the round-1 z-flux carried from the plane below is never used
         // before the first plane's)
         const Flux dF1z = fdiff(F1zn, getX(cz, 15, t));
@@ -513,12 +516,18 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         Face xl, xh, yl, yh;
         // (lanes whose final x or y states are never used skip reading
         // their traced states: the ring rows for x, the ring columns for y,
-        // and every lane in a segment's warm-up plane)
+        // and every lane in a segment's warm-up plane; the y-states are
+        // fetched with the x-states, ahead of the x corrections)
+        Face pyl = {}, pyh = {};
         {
             Face a = {}, b = {};
             if (pv && hD && hU) {
                 a = load_face_b(pp, wo, QLO(0, 0));
                 b = load_face_b(pp, wo, QHI(0, 0));
+            }
+            if (pv && hL && hR) {
+                pyl = load_face_b(pp, wo, QLO(1, 0));
+                pyh = load_face_b(pp, wo, QHI(1, 0));
             }
             const Flux dF2yz = getX(cz, 5, t);
             xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
@@ -527,11 +536,7 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
             if (fb && pv && hD && hU && rx_fh && ry_c && rp_c) err |= fb;
         }
         {
-            Face a = {}, b = {};
-            if (pv && hL && hR) {
-                a = load_face_b(pp, wo, QLO(1, 0));
-                b = load_face_b(pp, wo, QHI(1, 0));
-            }
+            const Face a = pyl, b = pyh;
             const Flux dF2xz = getX(cz, 0, t);
             yl = final_state2(a, dF2xz, dzx, fx2, fz2, gm1, igm1, fb);
             if (fb && pv && hL && hR && ry_f && rx_c && rp_c) err |= fb;
