@@ -238,6 +238,25 @@ __global__ void __launch_bounds__(256) k_sp_fused(SpArgs A, SpBatch B, int *err_
             (m ? v1 : v0) = v;
         }
     };
+    // the same in two parts inside the z-march: the partial densities and
+    // densities fetched with the iteration's other loads (by every lane, the
+    // second cell's index clamped into the plane: lanes past its 400 cells
+    // fetch a cell they do not store), the division where the plane is
+    // stored -- a division right after its loads (in a branch, as above)
+    // would make the iteration's later loads wait for them
+    auto xplane_ld = [&](int z, double (&sr)[4]) {
+        const int zq = zcl(z);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int r = min(t + 256 * m, kSRW * kSRW - 1);
+            const int rx = r % kSRW, ry = r / kSRW;
+            const int cx = min(max(x0 - 3 + rx, -ng), n0 + ng - 1);
+            const int cy = min(max(y0 - 3 + ry, -ng), n1 + ng - 1);
+            const unsigned bo = cbo(cx, cy, zq);
+            sr[2 * m] = ldb(Sg, bo);
+            sr[2 * m + 1] = ldb(rho, bo);
+        }
+    };
     auto xplane_put = [&](double v0, double v1) {
         xp[t] = v0;
         if (t + 256 < kSRW * kSRW) xp[t + 256] = v1;
@@ -255,8 +274,8 @@ __global__ void __launch_bounds__(256) k_sp_fused(SpArgs A, SpBatch B, int *err_
         // iteration's last barrier)
         // the next plane's X for the LDS plane, stored after this
         // iteration's second barrier (when every wave has traced plane q)
-        double xn0, xn1;
-        xplane(q + 1, xn0, xn1);
+        double xsr[4];
+        xplane_ld(q + 1, xsr);
         // own column: plane q+3 of the X window, the cell of plane q+1
         const double xnew = xown(q + 3);
         const Lam lam_n = lam_of(q + 1);
@@ -360,7 +379,8 @@ __global__ void __launch_bounds__(256) k_sp_fused(SpArgs A, SpBatch B, int *err_
         ed[0][t] = fy_h;
         ed[1][t] = fy_l;
         ed[2][t] = F3y;
-        xplane_put(xn0, xn1);
+        // ... and divided where they are stored
+        xplane_put(xsr[0] / xsr[1], xsr[2] / xsr[3]);
         const double F3xn = sp_next(F3x);
         const double dG3x = sp_flux(F3xn, fx_h, sp_next(fx_l)) - sp_flux(F3x, sp_prev(fx_h), fx_l);
         __syncthreads();
