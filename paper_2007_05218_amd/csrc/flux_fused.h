@@ -495,6 +495,26 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         }
         __syncthreads();
         // ---------------------------------------------------- final states
+        // the traced x/y states of plane q-1 for its final states, fetched
+        // before the final z state of plane q is formed so that their
+        // latency hides behind it (lanes whose final x or y states are never
+        // used skip them: the ring rows for x, the ring columns for y, and
+        // every lane in a segment's warm-up plane)
+        const int p = q - 1;
+        const bool pv = p >= T.z0;  // plane p is finished in this segment
+        const bool rp_c = inr(p, 0, n2 - 1);
+        Face pxl = {}, pxh = {}, pyl = {}, pyh = {};
+        {
+            gchar *pp = opaque_plane(ws.plane(p));
+            if (pv && hD && hU) {
+                pxl = load_face_b(pp, wo, QLO(0, 0));
+                pxh = load_face_b(pp, wo, QHI(0, 0));
+            }
+            if (pv && hL && hR) {
+                pyl = load_face_b(pp, wo, QLO(1, 0));
+                pyh = load_face_b(pp, wo, QHI(1, 0));
+            }
+        }
         // final z state of plane q
         const Flux dyx = fdiff(getX(yb.v, 0, tU), getX(yb.v, 0, t));
         const bool zin = hL && hR && hD && hU && rx_c && ry_c;
@@ -509,26 +529,9 @@ k_flux_fused(Launch L, double gamma, double cfl, double gx, double gy, double gz
         // y-difference of the (y|z) fluxes of plane q (used next plane)
         const Flux dyz = fdiff(getX(yb.v, 5, tU), getX(yb.v, 5, t));
         // final x and y states of plane q-1
-        const int p = q - 1;
-        const bool pv = p >= T.z0;  // plane p is finished in this segment
-        const bool rp_c = inr(p, 0, n2 - 1);
-        gchar *pp = opaque_plane(ws.plane(p));
         Face xl, xh, yl, yh;
-        // (lanes whose final x or y states are never used skip reading
-        // their traced states: the ring rows for x, the ring columns for y,
-        // and every lane in a segment's warm-up plane; the y-states are
-        // fetched with the x-states, ahead of the x corrections)
-        Face pyl = {}, pyh = {};
         {
-            Face a = {}, b = {};
-            if (pv && hD && hU) {
-                a = load_face_b(pp, wo, QLO(0, 0));
-                b = load_face_b(pp, wo, QHI(0, 0));
-            }
-            if (pv && hL && hR) {
-                pyl = load_face_b(pp, wo, QLO(1, 0));
-                pyh = load_face_b(pp, wo, QHI(1, 0));
-            }
+            const Face a = pxl, b = pxh;
             const Flux dF2yz = getX(cz, 5, t);
             xl = final_state2(a, dF2yz, dzy, fy2, fz2, gm1, igm1, fb);
             if (fb && pv && hD && hU && rx_f && ry_c && rp_c) err |= fb;
