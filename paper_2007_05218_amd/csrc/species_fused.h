@@ -276,6 +276,10 @@ __global__ void __launch_bounds__(256) k_sp_fused(SpArgs A, SpBatch B, int *err_
         // iteration's second barrier (when every wave has traced plane q)
         double xsr[4];
         xplane_ld(q + 1, xsr);
+        // the old partial density of the cell updated at the end of the
+        // z-step (plane p), fetched with the other loads (every lane, at its
+        // clamped column: the updating lanes' own cell)
+        const double s_old = ldb(Sg, cbo(xc, yc, zcl(p)));
         // own column: plane q+3 of the X window, the cell of plane q+1
         const double xnew = xown(q + 3);
         const Lam lam_n = lam_of(q + 1);
@@ -393,7 +397,7 @@ __global__ void __launch_bounds__(256) k_sp_fused(SpArgs A, SpBatch B, int *err_
             du = du + ay * dG3y;
             du = du + az * (G3zq - cz_G3z);
             const unsigned bo = cbo(x, y, p);
-            const double v = ldb(Sg, bo) - du;
+            const double v = s_old - du;
             if (!isfinite(v)) err |= HYDRO_ERR_NONFINITE;
             stb64(A.Sn + (long long)s * g.cs, bo, v);
         }
